@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Decompressed GB/s of the Gompresso/Bit decoder on one MI355X.
+
+Workload (the plain single-stream configuration): 256 MiB of seeded Zipf text,
+1 MiB blocks each cut into 16 KiB sub-blocks (64 per block), 32 KiB window,
+matches 3..258, code lengths <= 12.  The same data is compressed twice, as an
+ordinary LZ77 stream (resolved by Multi-Round Resolution) and as a
+Dependency-Elimination stream (resolved in one pass).  One step decodes both
+streams, each with one launch of the decoder (one workgroup per block); inputs
+and outputs stay resident in HBM for the whole timed region.
+
+The CPU oracle's compressor generates the compressed inputs and its decoder,
+run block-parallel over the host cores, is the CPU baseline.  Outputs of the
+timed runs are checked byte for byte against the original data.
+
+Prints one JSON line (see the field descriptions in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decompressed GB/s on 1 MI355X (MRR vs DE, % of HBM peak); p50/p99 request latency"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00519_amd", "csrc", f) for f in ("inflate.hip", "inflate.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inflate_traffic_zipf256.json")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def params(de: int):
+    import oracle
+    return oracle.CompressParams(block_size=1 << 20, window=32768, max_match=258, lmax=12, sub_target_raw=16384,
+                                 de=de, group=64)
+
+
+# ----------------------------------------------------------------------------- oracle leg
+def oracle_leg(size: int, threads: int, cpu_seconds: float):
+    """Input generation with the oracle's compressor, and the oracle decoder
+    timed block-parallel on the host cores (the paper's CPU method: a common
+    queue of blocks; each thread takes the next block when it finishes)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    import synth
+    t0 = time.time()
+    data = synth.zipf_text(size, threads=threads).tobytes()
+    log(f"generated {size} bytes of Zipf text in {time.time() - t0:.1f}s")
+    streams = {}
+    for mode, de in (("mrr", 0), ("de", 1)):
+        t0 = time.time()
+        streams[mode] = oracle.compress(data, params(de), threads=threads)
+        log(f"compressed ({mode}) to {len(streams[mode])} bytes (ratio {size / len(streams[mode]):.3f}) "
+            f"in {time.time() - t0:.1f}s")
+    baseline = None
+    if cpu_seconds > 0:
+        blocks = [(blk, len(blk)) for m in ("mrr", "de") for blk, _ in oracle.stream_blocks(streams[m])[0]]
+        raw_per_pass = 2 * size
+
+        def one(b):
+            rc, out = oracle.decompress_block(b[0])
+            assert rc == 0
+            return len(out)
+
+        passes, t0 = 0, time.time()
+        with ThreadPoolExecutor(threads) as ex:
+            while True:
+                assert sum(ex.map(one, blocks)) == raw_per_pass
+                passes += 1
+                el = time.time() - t0
+                if el * threads >= cpu_seconds or el > 30:
+                    break
+        baseline = {"value": round(raw_per_pass * passes / el / 1e9, 4), "unit": "GB/s", "cores": threads,
+                    "kind": "oracle",
+                    "sample": f"{passes} pass(es) over all {len(blocks)} blocks of both streams "
+                              f"({raw_per_pass >> 20} MiB decompressed per pass), block-parallel over "
+                              f"{threads} threads with a shared block queue; {el:.1f}s wall"}
+        log(f"cpu baseline: {baseline['value']} GB/s on {threads} threads ({passes} passes, {el:.1f}s)")
+    return data, streams, baseline
+
+
+# ----------------------------------------------------------------------------- GPU leg
+def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
+    import numpy as np
+    import torch
+
+    import paper_1606_00519_amd as gmp
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = gmp.Context(0)
+    size = len(data)
+    runs = {}
+    for mode in ("mrr", "de"):
+        s = streams[mode]
+        d_in = torch.frombuffer(bytearray(s), dtype=torch.uint8).to(dev)
+        out = torch.empty(size, dtype=torch.uint8, device=dev)
+        import oracle
+        blocks, bs, total = oracle.stream_blocks(s)
+        import struct
+        offs = struct.unpack_from(f"<{len(blocks) + 1}Q", s, 32)
+        jobs = []
+        for b, (blk, o) in enumerate(blocks):
+            info = gmp.block_info(blk)
+            jobs.append(gmp.Job(d_in.data_ptr() + offs[b], len(blk), out.data_ptr() + o, info["raw_len"],
+                                info["n_seq"], info["n_lit"], None))
+        status = torch.full((len(jobs),), 99, dtype=torch.int32, device=dev)
+        batch = ctx.batch_create(jobs, status)
+        runs[mode] = {"batch": batch, "out": out, "d_in": d_in, "status": status, "comp": len(s),
+                      "flags": gmp.MODE_MRR if mode == "mrr" else gmp.MODE_DE, "blocks": len(jobs)}
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        for k, mode in enumerate(("mrr", "de")):
+            r = runs[mode]
+            if evs is not None:
+                evs[mode][0].record(stream)
+            r["batch"].run(r["flags"], waves=1, persistent=False)
+            if evs is not None:
+                evs[mode][1].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev_list = [{m: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for m in ("mrr", "de")} for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(ev_list[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = {m: float(np.mean([e[m][0].elapsed_time(e[m][1]) for e in ev_list])) for m in ("mrr", "de")}
+    # correctness of what was timed
+    ref = np.frombuffer(data, np.uint8)
+    for mode, r in runs.items():
+        st = r["status"].cpu().numpy()
+        if not np.all(st == 0):
+            raise RuntimeError(f"{mode}: device status {st[st != 0][:8]}")
+        if not np.array_equal(r["out"].cpu().numpy(), ref):
+            raise RuntimeError(f"{mode}: GPU output differs from the original data")
+    for r in runs.values():
+        r["batch"].close()
+    ctx.close()
+    return wall, kernel_ms, {m: runs[m]["comp"] for m in runs}, runs["mrr"]["blocks"]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size-mib", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              f"blocks are independent, see DESIGN.md for how the decoder would shard.", file=sys.stderr)
+        return 2
+    size = args.size_mib << 20
+    data, streams, baseline = oracle_leg(size, args.threads, args.cpu_seconds)
+    wall, kernel_ms, comp, n_blocks = gpu_leg(data, streams, args.steps, args.warmup)
+    raw_step = 2 * size
+    ms_per_step = wall / args.steps * 1e3
+    value = raw_step / (wall / args.steps) / 1e9
+    modes = {}
+    for m in ("mrr", "de"):
+        t = kernel_ms[m] / 1e3
+        modes[m] = {"GBps": round(size / t / 1e9, 3), "kernel_ms": round(kernel_ms[m], 4),
+                    "ratio": round(size / comp[m], 4), "compressed_bytes": comp[m],
+                    "hbm_frac": round((size + comp[m]) / t / 1e9 / HBM_PEAK_GBPS, 5)}
+    dom = max(modes, key=lambda m: modes[m]["kernel_ms"])
+    achieved = (size + comp[dom]) / (kernel_ms[dom] / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == kernel_source_hash() and tr.get("mode") == dom and \
+                tr.get("size_mib") == args.size_mib:
+            traffic = tr.get("bytes_per_launch")
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic (seeded Zipf text, oracle-compressed)",
+        "config": {"workload": f"zipf-text {args.size_mib} MiB, 1 MiB blocks x 64 sub-blocks of 16 KiB, "
+                               f"window 32 KiB, matches 3-258, lmax 12; one MRR stream and one DE stream of "
+                               f"the same data per step",
+                   "raw_bytes_per_step": raw_step, "blocks_per_stream": n_blocks, "launch": "1 wave/block"},
+        "modes": modes,
+        "roofline": {"bound": "hbm", "kernel": f"inflate_kernel ({dom})", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5),
+                     "traffic": traffic},
+        "cpu_baseline": baseline,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

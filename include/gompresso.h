@@ -1,0 +1,152 @@
+/*
+ * gompresso.h — C ABI of the MI355X (gfx950) Gompresso/Bit decompressor.
+ *
+ * Decompresses the block format of arXiv 1606.00519 (section "Gompresso
+ * Overview"): independently compressed data blocks, each carrying two
+ * canonical Huffman codes (literal/length and offset) and a token stream cut
+ * into sub-blocks whose compressed sizes in bits are stored in the block
+ * (section "Parallel Compression").  Per block, one workgroup decodes every
+ * sub-block in its own lane (section "Huffman Decoding"), then one 64-lane
+ * wavefront resolves the sequences group by group (section "LZ77
+ * Decompression"): back-references of ordinary streams by Multi-Round
+ * Resolution (section "Multi-Round Resolution (MRR) of Nested
+ * back-references"), those of streams written with Dependency Elimination in
+ * a single pass (section "Dependency Elimination (DE)").
+ *
+ * Block layout (little-endian; the paper's format figure is not available,
+ * so this is the project's own concrete layout):
+ *   0   u32 magic 'GMPB'      4 u8 version(1)  5 u8 mode(0 ordinary, 1 DE)
+ *   6   u8 group G            7 u8 lmax (max code length)
+ *   8   u32 raw_len          12 u32 window (max distance, <= 32768)
+ *   16  u16 max_match (3..258)  18 u16 reserved(0)
+ *   20  u32 n_sub            24 u32 n_seq            28 u32 n_lit
+ *   32  u8 lens[160]  nibbles, low first: 286 literal/length then 30 distance
+ *   192 index: n_sub x {u32 bit_len, u32 n_seq, u32 n_lit, u32 raw_len}
+ *   then u32 payload_bytes, 12 zero bytes, payload (sub-block bitstreams,
+ *   each padded to 32 bits; sub-block i starts at 4*sum_{j<i} ceil(bit_len_j/32)).
+ * Bit order and alphabets follow RFC 1951 (LSB-first packing, codes MSB-first,
+ * length codes 257..285 and distance codes 0..29 with their extra bits);
+ * symbol 256 ends every sub-block.
+ * Stream layout: 'GMPF', u16 version, u16 flags, u32 block_size, u32 n_blocks,
+ *   u64 raw_total, u64 reserved, u64 block_off[n_blocks+1]; block b decodes to
+ *   output bytes [b*block_size, b*block_size + raw_len_b).
+ *
+ * Conventions for every call:
+ *   - "d_" pointers are device pointers (hipMalloc / torch CUDA tensors),
+ *     "h_" pointers are host pointers.  The caller owns every buffer it
+ *     passes; the library keeps no caller pointer after the call's stream
+ *     work completes.  Device input blocks must be 4-byte aligned.
+ *   - Calls that take a hipStream_t are asynchronous on that stream.
+ *   - Return value: host-detected errors synchronously (GMP_E*).  Errors
+ *     found on the device are written to a per-block status word (0 = OK,
+ *     otherwise a GMP_E* code) that the caller reads after synchronising.
+ *   - On any error, output contents are unspecified, but nothing is ever
+ *     written outside [out, out + out_len) of each block.
+ */
+#ifndef GOMPRESSO_H
+#define GOMPRESSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gmp_status;
+#define GMP_OK 0
+#define GMP_EINVAL -1   /* bad argument */
+#define GMP_EFORMAT -2  /* magic, version, header field, index or payload layout */
+#define GMP_ECODE -3    /* code lengths over lmax or not filling the code space; invalid symbol */
+#define GMP_EDIST -4    /* distance 0, beyond the bytes produced in the block, or beyond window */
+#define GMP_ELEN -5     /* match length outside [3, max_match] */
+#define GMP_ESIZE -6    /* out_len differs from the block's raw_len */
+#define GMP_ESUB -7     /* sub-block bit overrun, missing end symbol, count mismatch with the index */
+#define GMP_EDEVICE -8  /* HIP runtime error */
+#define GMP_ENOMEM -9   /* device or host allocation failed */
+#define GMP_EBUSY -10   /* no capacity (serving back-pressure) */
+#define GMP_ENOSYS -11  /* valid format feature this decoder does not implement (lmax > 13) */
+
+/* flags */
+#define GMP_MODE_AUTO 0u  /* single pass if the block says DE and its group is a multiple of 64, else MRR */
+#define GMP_MODE_MRR 1u   /* Multi-Round Resolution for every block (valid for any stream) */
+#define GMP_MODE_DE 2u    /* single pass; blocks whose header is not DE with group % 64 == 0 fail EINVAL */
+#define GMP_MODE_MASK 3u
+#define GMP_FLAG_STATS 0x100u /* record MRR rounds per 64-sequence group (gmp_job.d_rounds) */
+
+typedef struct gmp_ctx gmp_ctx;
+typedef struct gmp_batch gmp_batch;
+
+/* Header fields of one block, parsed on the host. */
+typedef struct {
+  uint32_t mode, group, lmax, raw_len, window, max_match;
+  uint32_t n_sub, n_seq, n_lit, payload_bytes;
+  uint64_t block_bytes; /* header + index + payload */
+} gmp_block_info;
+
+/* One block to decode.  The host fills n_seq / n_lit from gmp_block_info;
+ * they size the token workspace.  d_rounds (may be NULL) receives, with
+ * GMP_FLAG_STATS, one byte per 64-sequence group: the MRR rounds taken (1 for
+ * a single pass, 0 for a group without back-references; bit 7 set when the
+ * group was split because its output exceeded the on-chip window). */
+typedef struct {
+  const uint8_t* d_comp; /* device: the block (header, index, payload) */
+  uint64_t comp_len;     /* bytes readable at d_comp */
+  uint8_t* d_out;        /* device: where the block's raw_len bytes go */
+  uint64_t out_len;      /* must equal raw_len */
+  uint32_t n_seq, n_lit; /* from the block header */
+  uint8_t* d_rounds;     /* optional, ceil(n_seq/64) bytes */
+} gmp_job;
+
+/* Tuning of the batched kernel (section "Dependency on Data Block Size":
+ * sub-block count sets the Huffman parallelism per block). */
+typedef struct {
+  uint32_t waves_per_block; /* 1, 2, 4 or 8 wavefronts per workgroup (Huffman lanes = 64 x waves) */
+  uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
+  uint32_t workgroups;      /* persistent grid size (0 = 2 per compute unit) */
+  uint32_t reserved;
+} gmp_tuning;
+
+/* ---- context ------------------------------------------------------------------ */
+/* Creates a context on `device`: it owns the token workspace (grown on demand),
+ * job tables, status words and tuning.  Not thread-safe; use one per host thread. */
+gmp_status gmp_ctx_create(int device, gmp_ctx** out);
+void gmp_ctx_destroy(gmp_ctx* ctx);
+const char* gmp_strerror(gmp_status s);
+
+/* ---- host-side parsing ---------------------------------------------------------- */
+/* Parse a block header from a host copy of at least its first 208 + 16*n_sub bytes
+ * (len = bytes available).  Fails EFORMAT on bad magic/version/fields. */
+gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_block_info* out);
+/* Stream header: number of blocks, block size and total raw bytes. */
+gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks, uint32_t* block_size,
+                           uint64_t* raw_total);
+
+/* ---- single block (sections "Huffman Decoding" and "LZ77 Decompression") ---------- */
+/* Decode one block.  h_block: host copy of the block's header and index (the same
+ * bytes as d_block, at least gmp_block_info.block_bytes - payload_bytes long), used
+ * only to size the workspace.  d_status: device int32 that receives the block's
+ * status.  Asynchronous on `stream`. */
+gmp_status gmp_decompress_block(gmp_ctx* ctx, const uint8_t* d_block, size_t block_len, const void* h_block,
+                                size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
+                                void* stream);
+
+/* ---- whole stream (blocks in parallel, section "Parallel Decompression") ----------- */
+/* Decode a stream.  h_stream: host copy of the whole stream (for the block table and
+ * block headers); d_stream: the same bytes on the device.  d_status: n_blocks int32
+ * on the device.  out_len must equal the stream's raw_total. */
+gmp_status gmp_decompress_stream(gmp_ctx* ctx, const uint8_t* d_stream, const void* h_stream, size_t len,
+                                 uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags, void* stream);
+
+/* ---- batch of independent blocks (one launch over a device job table) ------------ */
+/* Upload a job table once; run it any number of times.  d_status: n_jobs int32 on
+ * the device.  The batch owns its device job table and workspace. */
+gmp_status gmp_batch_create(gmp_ctx* ctx, const gmp_job* h_jobs, uint32_t n_jobs, int32_t* d_status,
+                            gmp_batch** out);
+gmp_status gmp_batch_run(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, const gmp_tuning* tuning, void* stream);
+void gmp_batch_destroy(gmp_batch* batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

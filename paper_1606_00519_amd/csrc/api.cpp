@@ -1,0 +1,339 @@
+// Host side of the C ABI declared in include/gompresso.h: header parsing,
+// job tables, token workspace, launches.  Every decode step runs in the
+// kernels of inflate.hip; this file only marshals arguments.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gompresso.h"
+#include "inflate.h"
+
+namespace {
+
+constexpr uint32_t kMagicBlock = 0x42504D47u;   // 'GMPB'
+constexpr uint32_t kMagicStream = 0x46504D47u;  // 'GMPF'
+constexpr size_t kHdrBytes = 192;
+constexpr size_t kIdxBytes = 16;
+
+uint32_t rd32(const uint8_t* p) {
+  uint32_t v;
+  std::memcpy(&v, p, 4);
+  return v;
+}
+uint16_t rd16(const uint8_t* p) {
+  uint16_t v;
+  std::memcpy(&v, p, 2);
+  return v;
+}
+uint64_t rd64(const uint8_t* p) {
+  uint64_t v;
+  std::memcpy(&v, p, 8);
+  return v;
+}
+
+#define HIP_OK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return GMP_EDEVICE;     \
+  } while (0)
+
+}  // namespace
+
+struct gmp_ctx {
+  int device = 0;
+  int num_cu = 0;
+  gmpk::DevJob* d_jobs = nullptr;  // job table of the single-call paths
+  gmpk::DevJob* h_jobs = nullptr;  // pinned staging for it
+  size_t jobs_cap = 0;
+  uint8_t* d_ws = nullptr;  // token workspace of the single-call paths
+  size_t ws_cap = 0;
+  uint32_t* d_queue = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the last single-call launch
+  bool pending = false;
+};
+
+struct gmp_batch {
+  int device = 0;
+  uint32_t n = 0;
+  gmpk::DevJob* d_jobs = nullptr;
+  uint8_t* d_ws = nullptr;
+  uint32_t* d_queue = nullptr;
+  int num_cu = 0;
+};
+
+extern "C" const char* gmp_strerror(gmp_status s) {
+  switch (s) {
+    case GMP_OK: return "ok";
+    case GMP_EINVAL: return "invalid argument";
+    case GMP_EFORMAT: return "malformed block or stream layout";
+    case GMP_ECODE: return "invalid Huffman code or symbol";
+    case GMP_EDIST: return "invalid back-reference distance";
+    case GMP_ELEN: return "invalid match length";
+    case GMP_ESIZE: return "output size differs from the decompressed size";
+    case GMP_ESUB: return "sub-block bitstream does not match its index entry";
+    case GMP_EDEVICE: return "HIP runtime error";
+    case GMP_ENOMEM: return "out of memory";
+    case GMP_EBUSY: return "no capacity";
+    case GMP_ENOSYS: return "format feature not supported by this decoder";
+    default: return "unknown status";
+  }
+}
+
+extern "C" gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_block_info* out) {
+  if (!h_block || !out) return GMP_EINVAL;
+  const uint8_t* b = static_cast<const uint8_t*>(h_block);
+  if (len < kHdrBytes) return GMP_EFORMAT;
+  if (rd32(b) != kMagicBlock || b[4] != 1) return GMP_EFORMAT;
+  gmp_block_info i{};
+  i.mode = b[5];
+  i.group = b[6];
+  i.lmax = b[7];
+  i.raw_len = rd32(b + 8);
+  i.window = rd32(b + 12);
+  i.max_match = rd16(b + 16);
+  i.n_sub = rd32(b + 20);
+  i.n_seq = rd32(b + 24);
+  i.n_lit = rd32(b + 28);
+  if (i.mode > 1 || i.group < 1 || i.lmax < 1 || i.lmax > 15 || i.window < 1 || i.window > 32768 ||
+      i.max_match < 3 || i.max_match > 258 || rd16(b + 18) != 0)
+    return GMP_EFORMAT;
+  const uint64_t idx_end = kHdrBytes + kIdxBytes * (uint64_t)i.n_sub;
+  if (idx_end + 4 > len) return GMP_EFORMAT;
+  i.payload_bytes = rd32(b + idx_end);
+  i.block_bytes = idx_end + 16 + i.payload_bytes;
+  *out = i;
+  return GMP_OK;
+}
+
+extern "C" gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks, uint32_t* block_size,
+                                      uint64_t* raw_total) {
+  if (!h_stream) return GMP_EINVAL;
+  const uint8_t* s = static_cast<const uint8_t*>(h_stream);
+  if (len < 32 || rd32(s) != kMagicStream || rd16(s + 4) != 1) return GMP_EFORMAT;
+  const uint32_t bs = rd32(s + 8), nb = rd32(s + 12);
+  const uint64_t total = rd64(s + 16);
+  if (bs == 0 || nb != (total + bs - 1) / bs || 32 + 8 * ((uint64_t)nb + 1) > len) return GMP_EFORMAT;
+  if (n_blocks) *n_blocks = nb;
+  if (block_size) *block_size = bs;
+  if (raw_total) *raw_total = total;
+  return GMP_OK;
+}
+
+extern "C" gmp_status gmp_ctx_create(int device, gmp_ctx** out) {
+  if (!out) return GMP_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return GMP_EINVAL;
+  HIP_OK(hipSetDevice(device));
+  gmp_ctx* c = new (std::nothrow) gmp_ctx();
+  if (!c) return GMP_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&c->d_queue, 256) != hipSuccess) {
+    gmp_ctx_destroy(c);
+    return GMP_EDEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  *out = c;
+  return GMP_OK;
+}
+
+extern "C" void gmp_ctx_destroy(gmp_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->pending) (void)hipEventSynchronize(c->done);
+  if (c->d_jobs) (void)hipFree(c->d_jobs);
+  if (c->h_jobs) (void)hipHostFree(c->h_jobs);
+  if (c->d_ws) (void)hipFree(c->d_ws);
+  if (c->d_queue) (void)hipFree(c->d_queue);
+  if (c->done) (void)hipEventDestroy(c->done);
+  delete c;
+}
+
+namespace {
+
+// Make the context's single-call buffers large enough; waits for the previous
+// single call first, since it may still read them.
+gmp_status ctx_reserve(gmp_ctx* c, size_t n_jobs, size_t ws_bytes) {
+  if (c->pending) {
+    HIP_OK(hipEventSynchronize(c->done));
+    c->pending = false;
+  }
+  if (n_jobs > c->jobs_cap) {
+    if (c->d_jobs) (void)hipFree(c->d_jobs);
+    if (c->h_jobs) (void)hipHostFree(c->h_jobs);
+    c->d_jobs = nullptr;
+    c->h_jobs = nullptr;
+    c->jobs_cap = 0;
+    if (hipMalloc(&c->d_jobs, n_jobs * sizeof(gmpk::DevJob)) != hipSuccess) return GMP_ENOMEM;
+    if (hipHostMalloc(&c->h_jobs, n_jobs * sizeof(gmpk::DevJob), hipHostMallocDefault) != hipSuccess) return GMP_ENOMEM;
+    c->jobs_cap = n_jobs;
+  }
+  if (ws_bytes > c->ws_cap) {
+    if (c->d_ws) (void)hipFree(c->d_ws);
+    c->d_ws = nullptr;
+    c->ws_cap = 0;
+    if (hipMalloc(&c->d_ws, ws_bytes) != hipSuccess) return GMP_ENOMEM;
+    c->ws_cap = ws_bytes;
+  }
+  return GMP_OK;
+}
+
+gmp_status ctx_launch(gmp_ctx* c, size_t n_jobs, uint32_t flags, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(c->d_jobs, c->h_jobs, n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, s));
+  if (gmpk_launch(c->d_jobs, (uint32_t)n_jobs, flags, 1, 0, 0, c->d_queue, s) != 0) return GMP_EDEVICE;
+  HIP_OK(hipEventRecord(c->done, s));
+  c->pending = true;
+  return GMP_OK;
+}
+
+bool valid_flags(uint32_t flags) {
+  return (flags & ~(GMP_MODE_MASK | GMP_FLAG_STATS)) == 0 && (flags & GMP_MODE_MASK) != 3u;
+}
+
+}  // namespace
+
+extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, size_t block_len, const void* h_block,
+                                           size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status,
+                                           uint32_t flags, void* stream) {
+  if (!c || !d_block || !h_block || !d_status || !valid_flags(flags) || (flags & GMP_FLAG_STATS)) return GMP_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_block) & 3) return GMP_EINVAL;
+  gmp_block_info info;
+  gmp_status st = gmp_block_info_parse(h_block, h_len, &info);
+  if (st != GMP_OK) return st;
+  if (info.block_bytes > block_len) return GMP_EFORMAT;
+  if (out_len != info.raw_len) return GMP_ESIZE;
+  if (!d_out && out_len) return GMP_EINVAL;
+  HIP_OK(hipSetDevice(c->device));
+  const size_t ws = gmpk::workspace_bytes(info.n_seq, info.n_lit);
+  if ((st = ctx_reserve(c, 1, ws)) != GMP_OK) return st;
+  gmpk::DevJob& j = c->h_jobs[0];
+  j.comp = d_block;
+  j.comp_len = block_len;
+  j.out = d_out;
+  j.out_len = out_len;
+  j.ws = c->d_ws;
+  j.rounds = nullptr;
+  j.status = d_status;
+  j.n_seq = info.n_seq;
+  j.n_lit = info.n_lit;
+  return ctx_launch(c, 1, flags, static_cast<hipStream_t>(stream));
+}
+
+extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream, const void* h_stream, size_t len,
+                                            uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
+                                            void* stream) {
+  if (!c || !d_stream || !h_stream || !d_status || !valid_flags(flags) || (flags & GMP_FLAG_STATS)) return GMP_EINVAL;
+  uint32_t nb = 0, bs = 0;
+  uint64_t total = 0;
+  gmp_status st = gmp_stream_info(h_stream, len, &nb, &bs, &total);
+  if (st != GMP_OK) return st;
+  if (out_len != total) return GMP_ESIZE;
+  if (nb == 0) return GMP_OK;
+  if (!d_out) return GMP_EINVAL;
+  const uint8_t* hs = static_cast<const uint8_t*>(h_stream);
+  std::vector<gmp_block_info> infos(nb);
+  std::vector<uint64_t> offs(nb + 1);
+  uint64_t ws_total = 0;
+  for (uint32_t b = 0; b <= nb; b++) offs[b] = rd64(hs + 32 + 8 * (size_t)b);
+  for (uint32_t b = 0; b < nb; b++) {
+    if (offs[b] > offs[b + 1] || offs[b + 1] > len || (offs[b] & 3)) return GMP_EFORMAT;
+    if ((st = gmp_block_info_parse(hs + offs[b], offs[b + 1] - offs[b], &infos[b])) != GMP_OK) return st;
+    if (infos[b].block_bytes > offs[b + 1] - offs[b]) return GMP_EFORMAT;
+    const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
+    if (infos[b].raw_len != want) return GMP_ESIZE;
+    ws_total += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
+  }
+  HIP_OK(hipSetDevice(c->device));
+  if ((st = ctx_reserve(c, nb, ws_total)) != GMP_OK) return st;
+  uint64_t ws_off = 0;
+  for (uint32_t b = 0; b < nb; b++) {
+    gmpk::DevJob& j = c->h_jobs[b];
+    j.comp = d_stream + offs[b];
+    j.comp_len = offs[b + 1] - offs[b];
+    j.out = d_out + (uint64_t)b * bs;
+    j.out_len = infos[b].raw_len;
+    j.ws = c->d_ws + ws_off;
+    j.rounds = nullptr;
+    j.status = d_status + b;
+    j.n_seq = infos[b].n_seq;
+    j.n_lit = infos[b].n_lit;
+    ws_off += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
+  }
+  return ctx_launch(c, nb, flags, static_cast<hipStream_t>(stream));
+}
+
+extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32_t n_jobs, int32_t* d_status,
+                                       gmp_batch** out) {
+  if (!c || !out || (n_jobs && (!h_jobs || !d_status))) return GMP_EINVAL;
+  *out = nullptr;
+  HIP_OK(hipSetDevice(c->device));
+  std::vector<gmpk::DevJob> dj(n_jobs);
+  uint64_t ws_total = 0;
+  for (uint32_t i = 0; i < n_jobs; i++) {
+    const gmp_job& j = h_jobs[i];
+    if (!j.d_comp || (reinterpret_cast<uintptr_t>(j.d_comp) & 3) || (!j.d_out && j.out_len)) return GMP_EINVAL;
+    ws_total += gmpk::workspace_bytes(j.n_seq, j.n_lit);
+  }
+  gmp_batch* b = new (std::nothrow) gmp_batch();
+  if (!b) return GMP_ENOMEM;
+  b->device = c->device;
+  b->n = n_jobs;
+  b->num_cu = c->num_cu;
+  if (hipMalloc(&b->d_queue, 256) != hipSuccess || (n_jobs && hipMalloc(&b->d_jobs, n_jobs * sizeof(gmpk::DevJob)) != hipSuccess) ||
+      (ws_total && hipMalloc(&b->d_ws, ws_total) != hipSuccess)) {
+    gmp_batch_destroy(b);
+    return GMP_ENOMEM;
+  }
+  uint64_t ws_off = 0;
+  for (uint32_t i = 0; i < n_jobs; i++) {
+    const gmp_job& j = h_jobs[i];
+    gmpk::DevJob& d = dj[i];
+    d.comp = j.d_comp;
+    d.comp_len = j.comp_len;
+    d.out = j.d_out;
+    d.out_len = j.out_len;
+    d.ws = b->d_ws + ws_off;
+    d.rounds = j.d_rounds;
+    d.status = d_status + i;
+    d.n_seq = j.n_seq;
+    d.n_lit = j.n_lit;
+    ws_off += gmpk::workspace_bytes(j.n_seq, j.n_lit);
+  }
+  if (n_jobs && hipMemcpy(b->d_jobs, dj.data(), n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice) != hipSuccess) {
+    gmp_batch_destroy(b);
+    return GMP_EDEVICE;
+  }
+  *out = b;
+  return GMP_OK;
+}
+
+extern "C" gmp_status gmp_batch_run(gmp_ctx* c, gmp_batch* b, uint32_t flags, const gmp_tuning* tuning, void* stream) {
+  if (!c || !b || !valid_flags(flags)) return GMP_EINVAL;
+  uint32_t waves = 1, persistent = 0, wgs = 0;
+  if (tuning) {
+    waves = tuning->waves_per_block;
+    persistent = tuning->persistent;
+    wgs = tuning->workgroups;
+  }
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return GMP_EINVAL;
+  if (persistent && wgs == 0) wgs = 2u * (uint32_t)b->num_cu;
+  if (b->n == 0) return GMP_OK;
+  HIP_OK(hipSetDevice(b->device));
+  if (gmpk_launch(b->d_jobs, b->n, flags, waves, persistent, wgs, b->d_queue, static_cast<hipStream_t>(stream)) != 0)
+    return GMP_EDEVICE;
+  return GMP_OK;
+}
+
+extern "C" void gmp_batch_destroy(gmp_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  delete b;
+}

@@ -1,0 +1,37 @@
+// Device job descriptor and launch entry shared by the kernels and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GMPK_MODE_AUTO 0u
+#define GMPK_MODE_MRR 1u
+#define GMPK_MODE_DE 2u
+#define GMPK_MODE_MASK 3u
+#define GMPK_FLAG_STATS 0x100u
+
+namespace gmpk {
+
+constexpr int kMaxWaves = 8;
+
+// One block to decode (device copy of a host job, 64 bytes).
+struct DevJob {
+  const uint8_t* comp;  // the block: header, index, payload
+  uint64_t comp_len;
+  uint8_t* out;         // raw_len output bytes
+  uint64_t out_len;
+  uint8_t* ws;          // token workspace: n_seq 8-byte records, then n_lit bytes + 64 bytes of slack
+  uint8_t* rounds;      // optional per-group round counts
+  int32_t* status;      // the block's status word
+  uint32_t n_seq, n_lit;
+};
+static_assert(sizeof(DevJob) == 64, "DevJob layout");
+
+// workspace bytes for one block
+inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
+  return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256;
+}
+
+}  // namespace gmpk
+
+extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t waves,
+                           uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, hipStream_t stream);

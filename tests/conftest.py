@@ -18,3 +18,15 @@ def _oracle_built():
     if not os.path.exists(oracle._LIB_PATH):
         oracle.build(force=False)
     yield
+
+
+@pytest.fixture(scope="session")
+def hip_lib_built():
+    """The HIP library is built in-tree by __graft_entry__.build(); build it here if it is missing."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("gmp_build", os.path.join(ROOT, "paper_1606_00519_amd", "build.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    if not os.path.exists(b.LIB):
+        b.build()
+    return b.LIB

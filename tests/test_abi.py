@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every entry point include/gompresso.h
+declares; the host-only header parsers agree with the oracle.  No GPU needed
+(no decode call is made)."""
+import ctypes
+import os
+import re
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gompresso.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(hip_lib_built):
+    lib = ctypes.CDLL(hip_lib_built)
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    import paper_1606_00519_amd as gmp
+    assert set(gmp.EXPORTS) == set(names)
+
+
+def test_host_parsers_agree_with_oracle(hip_lib_built):
+    import paper_1606_00519_amd as gmp
+    data = synth.zipf_text(700_000).tobytes()
+    s = oracle.compress(data, oracle.CompressParams(block_size=1 << 18, de=1))
+    assert gmp.stream_info(s) == (3, 1 << 18, len(data))
+    for blk, _ in oracle.stream_blocks(s)[0]:
+        mine, ref = gmp.block_info(blk), oracle.block_info(blk)
+        for k in ("mode", "group", "lmax", "raw_len", "window", "max_match", "n_sub", "n_seq", "n_lit",
+                  "payload_bytes", "block_bytes"):
+            assert mine[k] == ref[k], k
+
+
+def test_host_parser_rejects_bad_headers(hip_lib_built):
+    import pytest
+    import paper_1606_00519_amd as gmp
+    blk = bytearray(oracle.compress_block(b"hello hello hello", oracle.CompressParams()))
+    for off, val in ((0, 0), (4, 2), (5, 7), (7, 0), (18, 1)):
+        b = bytearray(blk)
+        b[off] = val
+        with pytest.raises(gmp.GmpError) as e:
+            gmp.block_info(bytes(b))
+        assert e.value.status == gmp.EFORMAT
+    assert gmp.strerror(gmp.ESUB)
