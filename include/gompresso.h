@@ -23,7 +23,7 @@
  *   32  u8 lens[160]  nibbles, low first: 286 literal/length then 30 distance
  *   192 index: n_sub x {u32 bit_len, u32 n_seq, u32 n_lit, u32 raw_len}
  *   then u32 payload_bytes, 12 zero bytes, payload (sub-block bitstreams,
- *   each padded to 32 bits; sub-block i starts at 4*sum_{j<i} ceil(bit_len_j/32)).
+ *   each padded to 128 bits; sub-block i starts at 16*sum_{j<i} ceil(bit_len_j/128)).
  * Bit order and alphabets follow RFC 1951 (LSB-first packing, codes MSB-first,
  * length codes 257..285 and distance codes 0..29 with their extra bits);
  * symbol 256 ends every sub-block.
@@ -35,7 +35,7 @@
  *   - "d_" pointers are device pointers (hipMalloc / torch CUDA tensors),
  *     "h_" pointers are host pointers.  The caller owns every buffer it
  *     passes; the library keeps no caller pointer after the call's stream
- *     work completes.  Device input blocks must be 4-byte aligned.
+ *     work completes.  Device input blocks must be 16-byte aligned.
  *   - Calls that take a hipStream_t are asynchronous on that stream.
  *   - Return value: host-detected errors synchronously (GMP_E*).  Errors
  *     found on the device are written to a per-block status word (0 = OK,
@@ -85,10 +85,12 @@ typedef struct {
 } gmp_block_info;
 
 /* One block to decode.  The host fills n_seq / n_lit from gmp_block_info;
- * they size the token workspace.  d_rounds (may be NULL) receives, with
- * GMP_FLAG_STATS, one byte per 64-sequence group: the MRR rounds taken (1 for
- * a single pass, 0 for a group without back-references; bit 7 set when the
- * group was split because its output exceeded the on-chip window). */
+ * they size the token workspace.  With GMP_FLAG_STATS, d_rounds (may be NULL)
+ * receives one byte per 64-sequence group: the MRR rounds taken (1 for a
+ * single pass, 0 for a group without back-references; bit 7 set when the
+ * group was split because its output exceeded the on-chip window), and
+ * d_times (may be NULL) four device wall-clock stamps (100 MHz ticks): start,
+ * tables built, sub-blocks decoded, back-references resolved. */
 typedef struct {
   const uint8_t* d_comp; /* device: the block (header, index, payload) */
   uint64_t comp_len;     /* bytes readable at d_comp */
@@ -96,6 +98,7 @@ typedef struct {
   uint64_t out_len;      /* must equal raw_len */
   uint32_t n_seq, n_lit; /* from the block header */
   uint8_t* d_rounds;     /* optional, ceil(n_seq/64) bytes */
+  uint64_t* d_times;     /* optional, 4 x uint64 */
 } gmp_job;
 
 /* Tuning of the batched kernel (section "Dependency on Data Block Size":

@@ -296,7 +296,7 @@ int gmpref_encode_block(const gmpref_seq* seqs, size_t n_seq, const uint8_t* lit
   gmpref_canonical_codes(lens, N_LL, ll_code);
   gmpref_canonical_codes(lens + N_LL, N_D, d_code);
 
-  /* payload: each sub-block separately, padded to 32 bits */
+  /* payload: each sub-block separately, padded to 128 bits */
   buf_t pay = {0, 0, 0};
   uint32_t* sub_bits = (uint32_t*)calloc(n_sub ? n_sub : 1, sizeof(uint32_t));
   uint32_t* sub_nlit = (uint32_t*)calloc(n_sub ? n_sub : 1, sizeof(uint32_t));
@@ -328,7 +328,7 @@ int gmpref_encode_block(const gmpref_seq* seqs, size_t n_seq, const uint8_t* lit
       }
     }
     bw_code(&w, ll_code[SYM_END], lens[SYM_END]);
-    while (w.nbits & 31) bw_bit(&w, 0); /* pad to a 32-bit boundary */
+    while (w.nbits & 127) bw_bit(&w, 0); /* pad to a 128-bit boundary */
     /* the recorded size excludes the padding */
     err = w.err;
     sub_nlit[s] = (uint32_t)nlit;
@@ -718,7 +718,7 @@ static int decode_tokens(const uint8_t* blk, size_t len, gmpref_block_info* info
   uint64_t words = 0, s_seq = 0, s_lit = 0, s_raw = 0;
   for (uint32_t s = 0; s < info->n_sub; s++) {
     const uint8_t* e = idx + IDX_ENTRY * s;
-    words += (rd32(e) + 31) / 32;
+    words += 4 * (((uint64_t)rd32(e) + 127) / 128);
     s_seq += rd32(e + 4);
     s_lit += rd32(e + 8);
     s_raw += rd32(e + 12);
@@ -745,7 +745,7 @@ static int decode_tokens(const uint8_t* blk, size_t len, gmpref_block_info* info
     const uint8_t* e = idx + IDX_ENTRY * s;
     uint32_t bit_len = rd32(e), want_seq = rd32(e + 4), want_lit = rd32(e + 8), want_raw = rd32(e + 12);
     bitr r = {payload + byte_off, bit_len, 0};
-    byte_off += 4 * (uint64_t)((bit_len + 31) / 32);
+    byte_off += 16 * (((uint64_t)bit_len + 127) / 128);
     uint64_t got_seq = 0, got_lit = 0, sub_raw0 = produced;
     uint32_t run = 0;
     for (;;) {
@@ -911,7 +911,7 @@ int gmpref_validate_block(const uint8_t* blk, size_t len) {
   uint64_t byte_off = 0;
   for (uint32_t s = 0; s < info.n_sub && rc == 0; s++) {
     uint32_t bit_len = rd32(idx + IDX_ENTRY * s);
-    uint64_t padded = 32 * (uint64_t)((bit_len + 31) / 32);
+    uint64_t padded = 128 * (((uint64_t)bit_len + 127) / 128);
     for (uint64_t b = bit_len; b < padded; b++)
       if ((payload[byte_off + b / 8] >> (b % 8)) & 1) rc = GMPREF_ESUB;
     byte_off += padded / 8;

@@ -51,8 +51,8 @@
  *              u32 raw_len   decompressed bytes of the sub-block
  *   off 192 + 16*n_sub   u32 payload_bytes
  *   then 12 zero bytes (payload starts 16-byte aligned)
- *   payload: the sub-block bitstreams, each padded to a multiple of 32 bits,
- *            so sub-block i starts at byte 4 * sum_{j<i} ceil(bit_len_j/32).
+ *   payload: the sub-block bitstreams, each padded to a multiple of 128 bits,
+ *            so sub-block i starts at byte 16 * sum_{j<i} ceil(bit_len_j/128).
  *
  * Bitstream of a sub-block (RFC 1951 section 3.1.1 packing): bits are read
  * least-significant first from consecutive bytes; Huffman codes are stored
