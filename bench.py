@@ -122,8 +122,14 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
                                 info["n_seq"], info["n_lit"], None))
         status = torch.full((len(jobs),), 99, dtype=torch.int32, device=dev)
         batch = ctx.batch_create(jobs, status)
-        runs[mode] = {"batch": batch, "out": out, "d_in": d_in, "status": status, "comp": len(s),
-                      "flags": gmp.MODE_MRR if mode == "mrr" else gmp.MODE_DE, "blocks": len(jobs)}
+        # a second job table over the same buffers records per-phase device timestamps
+        times = torch.zeros((len(jobs), 4), dtype=torch.int64, device=dev)
+        for b, j in enumerate(jobs):
+            j.d_times = times.data_ptr() + 32 * b
+        tbatch = ctx.batch_create(jobs, status)
+        runs[mode] = {"batch": batch, "tbatch": tbatch, "times": times, "out": out, "d_in": d_in,
+                      "status": status, "comp": len(s), "flags": gmp.MODE_MRR if mode == "mrr" else gmp.MODE_DE,
+                      "blocks": len(jobs)}
     stream = torch.cuda.current_stream()
 
     def step(evs=None):
@@ -149,6 +155,19 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
     kernel_ms = {m: float(np.mean([e[m][0].elapsed_time(e[m][1]) for e in ev_list])) for m in ("mrr", "de")}
     # correctness of what was timed
     ref = np.frombuffer(data, np.uint8)
+    phases = {}
+    for mode, r in runs.items():
+        if not np.array_equal(r["out"].cpu().numpy(), ref):
+            raise RuntimeError(f"{mode}: GPU output differs from the original data")
+        # untimed extra run: device wall-clock stamps per block (100 MHz ticks)
+        r["tbatch"].run(r["flags"] | gmp.FLAG_STATS, waves=1, persistent=False)
+        torch.cuda.synchronize()
+        t = r["times"].cpu().numpy().astype(np.int64)
+        d = np.diff(t, axis=1) * 10 / 1e3  # microseconds: tables, sub-block decode, resolution
+        span = (t[:, 3].max() - t[:, 0].min()) * 10 / 1e3
+        phases[mode] = {"tables_us": round(float(d[:, 0].mean()), 2), "huffman_us": round(float(d[:, 1].mean()), 2),
+                        "huffman_us_max": round(float(d[:, 1].max()), 2), "lz_us": round(float(d[:, 2].mean()), 2),
+                        "lz_us_max": round(float(d[:, 2].max()), 2), "launch_span_us": round(float(span), 2)}
     for mode, r in runs.items():
         st = r["status"].cpu().numpy()
         if not np.all(st == 0):
@@ -157,8 +176,9 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
             raise RuntimeError(f"{mode}: GPU output differs from the original data")
     for r in runs.values():
         r["batch"].close()
+        r["tbatch"].close()
     ctx.close()
-    return wall, kernel_ms, {m: runs[m]["comp"] for m in runs}, runs["mrr"]["blocks"]
+    return wall, kernel_ms, {m: runs[m]["comp"] for m in runs}, runs["mrr"]["blocks"], phases
 
 
 def main() -> int:
@@ -169,6 +189,9 @@ def main() -> int:
     ap.add_argument("--size-mib", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device-to-device copy of the output size (a reference kernel "
+                         "for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -176,7 +199,14 @@ def main() -> int:
         return 2
     size = args.size_mib << 20
     data, streams, baseline = oracle_leg(size, args.threads, args.cpu_seconds)
-    wall, kernel_ms, comp, n_blocks = gpu_leg(data, streams, args.steps, args.warmup)
+    if args.copy_probe:
+        import torch
+        src = torch.empty(size, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads and writes exactly `size` bytes
+        torch.cuda.synchronize()
+        del src, dst
+    wall, kernel_ms, comp, n_blocks, phases = gpu_leg(data, streams, args.steps, args.warmup)
     raw_step = 2 * size
     ms_per_step = wall / args.steps * 1e3
     value = raw_step / (wall / args.steps) / 1e9
@@ -185,7 +215,7 @@ def main() -> int:
         t = kernel_ms[m] / 1e3
         modes[m] = {"GBps": round(size / t / 1e9, 3), "kernel_ms": round(kernel_ms[m], 4),
                     "ratio": round(size / comp[m], 4), "compressed_bytes": comp[m],
-                    "hbm_frac": round((size + comp[m]) / t / 1e9 / HBM_PEAK_GBPS, 5)}
+                    "hbm_frac": round((size + comp[m]) / t / 1e9 / HBM_PEAK_GBPS, 5), "phases": phases[m]}
     dom = max(modes, key=lambda m: modes[m]["kernel_ms"])
     achieved = (size + comp[dom]) / (kernel_ms[dom] / 1e3) / 1e9
     traffic = None

@@ -104,7 +104,8 @@ typedef struct {
 /* Tuning of the batched kernel (section "Dependency on Data Block Size":
  * sub-block count sets the Huffman parallelism per block). */
 typedef struct {
-  uint32_t waves_per_block; /* 1, 2, 4 or 8 wavefronts per workgroup (Huffman lanes = 64 x waves) */
+  uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2 or 4 (Huffman lanes = 64 x waves); each
+                               workgroup adds one fetcher wavefront that streams HBM into LDS */
   uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
   uint32_t workgroups;      /* persistent grid size (0 = 2 per compute unit) */
   uint32_t reserved;

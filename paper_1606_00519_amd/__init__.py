@@ -45,7 +45,7 @@ class BlockInfo(C.Structure):
 
 class Job(C.Structure):
     _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("d_out", C.c_void_p), ("out_len", C.c_uint64),
-                ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p)]
+                ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p)]
 
 
 class Tuning(C.Structure):

@@ -217,7 +217,9 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
   j.out = d_out;
   j.out_len = out_len;
   j.ws = c->d_ws;
+  j.ws_len = ws;
   j.rounds = nullptr;
+  j.times = nullptr;
   j.status = d_status;
   j.n_seq = info.n_seq;
   j.n_lit = info.n_lit;
@@ -258,11 +260,13 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     j.out = d_out + (uint64_t)b * bs;
     j.out_len = infos[b].raw_len;
     j.ws = c->d_ws + ws_off;
+    j.ws_len = gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
     j.rounds = nullptr;
+    j.times = nullptr;
     j.status = d_status + b;
     j.n_seq = infos[b].n_seq;
     j.n_lit = infos[b].n_lit;
-    ws_off += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
+    ws_off += j.ws_len;
   }
   return ctx_launch(c, nb, flags, static_cast<hipStream_t>(stream));
 }
@@ -298,11 +302,13 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     d.out = j.d_out;
     d.out_len = j.out_len;
     d.ws = b->d_ws + ws_off;
+    d.ws_len = gmpk::workspace_bytes(j.n_seq, j.n_lit);
     d.rounds = j.d_rounds;
+    d.times = j.d_times;
     d.status = d_status + i;
     d.n_seq = j.n_seq;
     d.n_lit = j.n_lit;
-    ws_off += gmpk::workspace_bytes(j.n_seq, j.n_lit);
+    ws_off += d.ws_len;
   }
   if (n_jobs && hipMemcpy(b->d_jobs, dj.data(), n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice) != hipSuccess) {
     gmp_batch_destroy(b);
@@ -320,7 +326,7 @@ extern "C" gmp_status gmp_batch_run(gmp_ctx* c, gmp_batch* b, uint32_t flags, co
     persistent = tuning->persistent;
     wgs = tuning->workgroups;
   }
-  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return GMP_EINVAL;
+  if (waves != 1 && waves != 2 && waves != 4) return GMP_EINVAL;
   if (persistent && wgs == 0) wgs = 2u * (uint32_t)b->num_cu;
   if (b->n == 0) return GMP_OK;
   HIP_OK(hipSetDevice(b->device));

@@ -11,20 +11,22 @@
 
 namespace gmpk {
 
-constexpr int kMaxWaves = 8;
+constexpr int kMaxDecWaves = 4;  // decoder wavefronts per workgroup (plus one fetcher)
 
-// One block to decode (device copy of a host job, 64 bytes).
+// One block to decode (device copy of a host job, 80 bytes).
 struct DevJob {
   const uint8_t* comp;  // the block: header, index, payload
   uint64_t comp_len;
   uint8_t* out;         // raw_len output bytes
   uint64_t out_len;
-  uint8_t* ws;          // token workspace: n_seq 8-byte records, then n_lit bytes + 64 bytes of slack
+  uint8_t* ws;          // token workspace: n_seq 8-byte records, then n_lit bytes + slack
+  uint64_t ws_len;
   uint8_t* rounds;      // optional per-group round counts
+  uint64_t* times;      // optional phase timestamps (4 per block)
   int32_t* status;      // the block's status word
   uint32_t n_seq, n_lit;
 };
-static_assert(sizeof(DevJob) == 64, "DevJob layout");
+static_assert(sizeof(DevJob) == 80, "DevJob layout");
 
 // workspace bytes for one block
 inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
@@ -33,5 +35,5 @@ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
 
 }  // namespace gmpk
 
-extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t waves,
+extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t dec_waves,
                            uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, hipStream_t stream);

@@ -1,17 +1,24 @@
 // Gompresso/Bit intra-block parallel Inflate for gfx950 (MI355X).
 //
 // One workgroup decodes one data block (arXiv 1606.00519, section
-// "Parallel Decompression"):
+// "Parallel Decompression").  The workgroup has kDec decoder wavefronts and
+// one fetcher wavefront.  The fetcher performs every HBM read of the hot
+// loops as asynchronous HBM->LDS copies (global_load_lds_dwordx4) and is the
+// only wavefront that waits on the vector-memory counter; the decoder
+// wavefronts work out of LDS and only issue stores, which never stall them.
+// The two sides hand data over through progress counters in LDS.
+//
 //   A0  header and sub-block index checks; sub-block offsets by block-wide
 //       prefix sums over the sizes stored in the index (section "Huffman
-//       Decoding": offsets come from the sub-block sizes in the header);
+//       Decoding": the decoder locates sub-blocks from their sizes);
 //   A1  both canonical Huffman codes expanded into 2^lmax-entry lookup tables
 //       in LDS, one lookup per symbol;
-//   A2  every lane decodes one sub-block: sequence records and literal bytes
-//       go to a per-block token workspace (the paper's token stream);
-//   A3  wavefront 0 walks the sequences in groups of 64 (one per lane) and
-//       computes literal source and output offsets with two DPP prefix sums
-//       (section "LZ77 Decompression", reading sequences / copying literals);
+//   A2  every decoder lane decodes one sub-block whose bitstream the fetcher
+//       streams into a per-lane LDS ring; sequence records and literal bytes
+//       go to the block's token workspace (the paper's token stream);
+//   A3  decoder wavefront 0 walks the sequences in groups of 64 (one per
+//       lane) and computes literal source and output offsets with two DPP
+//       prefix sums (section "LZ77 Decompression");
 //   A4  literal strings are copied into an on-chip output window (LDS ring);
 //   A5  back-references of ordinary streams: Multi-Round Resolution — each
 //       round, the high-water mark is the destination of the lowest pending
@@ -21,10 +28,11 @@
 //       back-references");
 //   A6  back-references of Dependency-Elimination streams: one pass, no
 //       checks (section "Dependency Elimination (DE)");
-//   the window is flushed to HBM in 1 KiB coalesced chunks.
+//   the window is flushed to HBM in coalesced 16-byte-per-lane stores, and
+//   during A3-A6 the fetcher streams the token workspace into LDS.
 //
 // All arithmetic is integer.  No device memory outside the job's output,
-// workspace, rounds and status buffers is written.
+// workspace, rounds, times and status words is written.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,6 +40,37 @@
 #include "inflate.h"
 
 namespace gmpk {
+
+// Device-memory pointers are handled as address-space-1 (global) pointers, so
+// that every access compiles to a global_* instruction: flat accesses would be
+// ordered against LDS traffic and force waits on both counters.
+#define GMEM __attribute__((address_space(1)))
+struct __attribute__((packed)) Packed16 {
+  uint32_t x, y, z, w;
+};
+struct __attribute__((packed)) Packed4 {
+  uint32_t v;
+};
+template <typename T>
+__device__ __forceinline__ GMEM T* gmem(T* p) {
+  return (GMEM T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GMEM T* gmem(const T* p) {
+  return (const GMEM T*)p;
+}
+__device__ __forceinline__ uint4 gload16(const GMEM uint8_t* p) {
+  const GMEM Packed16* t = (const GMEM Packed16*)p;
+  return make_uint4(t->x, t->y, t->z, t->w);
+}
+__device__ __forceinline__ void gstore16(GMEM uint8_t* p, uint4 v) {
+  GMEM Packed16* t = (GMEM Packed16*)p;
+  t->x = v.x;
+  t->y = v.y;
+  t->z = v.z;
+  t->w = v.w;
+}
+__device__ __forceinline__ uint32_t gload32(const GMEM uint8_t* p) { return ((const GMEM Packed4*)p)->v; }
 
 constexpr uint32_t kMagicBlock = 0x42504D47u;  // 'GMPB'
 constexpr uint32_t kHdrBytes = 192;
@@ -43,7 +82,11 @@ constexpr uint32_t kLutSize = 1u << kLutBits;
 constexpr uint32_t kRing = 65536;  // on-chip output window
 constexpr uint32_t kRingMask = kRing - 1;
 constexpr uint32_t kSpanCap = kRing - 32768;  // most output one resolution pass holds (window <= 32768)
-constexpr uint32_t kFlushChunk = 1024;        // 64 lanes x 16 bytes
+constexpr uint32_t kStageBytes = 32768;       // staging area: bit rings, then token rings
+constexpr uint32_t kRecRing = 2048;           // staged sequence records (8 bytes each)
+constexpr uint32_t kLitRing = 8192;           // staged literal bytes
+constexpr uint32_t kLitStagedMax = 4096;      // larger literal groups read HBM directly
+constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
 
 // status codes (same values as the public header)
 constexpr int kOK = 0, kEINVAL = -1, kEFORMAT = -2, kECODE = -3, kEDIST = -4, kELEN = -5, kESIZE = -6,
@@ -98,33 +141,66 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
-struct Shared {
-  union {
-    uint32_t lut[2 * kLutSize];  // literal/length table, then distance table
-    uint8_t ring[kRing];         // output window (after decoding)
-  };
+// LDS progress counters: release after the data they announce, acquire before
+// reading that data.
+__device__ __forceinline__ uint32_t lds_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+constexpr int kMaxLanes = 64 * kMaxDecWaves;
+
+struct Misc {
   uint8_t lens[kNumLL + kNumD];
-  uint16_t sorted[kNumLL];  // symbols of one code in canonical order
-  uint32_t count[16], first[16], offs[17];
-  uint32_t wave_sum[4][kMaxWaves];
+  uint32_t count[16], first[16];
+  uint32_t wave_sum[4][kMaxDecWaves + 1];
+  uint32_t sub_woff[kMaxLanes];  // first payload word of each lane's sub-block
+  uint32_t sub_nw[kMaxLanes];    // its words, a multiple of 4 (0: nothing to fetch)
+  uint32_t rd[kMaxLanes];        // decoder -> fetcher: words taken from the lane's bit ring
+  uint32_t avail[kMaxLanes];     // fetcher -> decoder: words present in the lane's bit ring
+  uint32_t rec_avail, lit_avail;  // fetcher -> resolver: records / literal bytes staged
+  uint32_t rec_cons, lit_cons;    // resolver -> fetcher: records / literal bytes consumed
+  uint32_t next_job;
   int err;
 };
 
-__device__ __forceinline__ void set_err(Shared& sh, int e) { atomicCAS(&sh.err, 0, e); }
+// Workgroup-shared memory.
+__shared__ __attribute__((aligned(16))) uint32_t s_big[kRing / 4];     // lookup tables, then the output window
+__shared__ __attribute__((aligned(16))) uint4 s_stage[kStageBytes / 16];  // bit rings, then staged tokens
+__shared__ Misc s_misc;
+
+__device__ __forceinline__ uint8_t* ring_ptr() { return reinterpret_cast<uint8_t*>(s_big); }
+__device__ __forceinline__ uint2* rec_ring() { return reinterpret_cast<uint2*>(s_stage); }
+__device__ __forceinline__ uint8_t* lit_ring() { return reinterpret_cast<uint8_t*>(s_stage) + 8 * kRecRing; }
+
+__device__ __forceinline__ void set_err(int e) { atomicCAS(&s_misc.err, 0, e); }
+
+// Asynchronous copy of 1 KiB from HBM into LDS: lane l moves the 16 bytes at
+// its src to lds + 16*l (lds is the same for all lanes).
+__device__ __forceinline__ void dma16(const GMEM uint8_t* src, void* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+// Wait until every memory operation this wavefront issued has completed.
+__device__ __forceinline__ void wait_all_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ---------------------------------------------------------------- A1 tables
-// Canonical code of one alphabet -> lookup table (entry-centric fill: the
-// lmax stream bits of an index, read MSB-first, fall into exactly one length's
-// code range when the code fills the code space).
+// Canonical code of one alphabet -> lookup table.  Codes of each length are
+// consecutive in symbol order (RFC 1951 section 3.2.2); a symbol's rank within
+// its length comes from ballots over 64-symbol chunks, and its lane writes
+// every table entry whose low bits are its (bit-reversed) code.
 template <int kThreads>
-__device__ void build_table(Shared& sh, const uint8_t* lens, uint32_t nsym, uint32_t lmax, uint32_t* lut,
-                            bool is_dist) {
+__device__ void build_table(const uint8_t* lens, uint32_t nsym, uint32_t lmax, uint32_t* lut, bool is_dist) {
+  Misc& sh = s_misc;
   const uint32_t t = threadIdx.x;
+  const uint32_t lane = t & 63, wave = t >> 6;
+  constexpr uint32_t kWaves = kThreads / 64;
   if (t < 16) sh.count[t] = 0;
   __syncthreads();
   for (uint32_t s = t; s < nsym; s += kThreads) {
     uint32_t l = lens[s];
-    if (l > lmax) set_err(sh, kECODE);
+    if (l > lmax) set_err(kECODE);
     if (l) atomicAdd(&sh.count[l], 1u);
   }
   __syncthreads();
@@ -136,84 +212,72 @@ __device__ void build_table(Shared& sh, const uint8_t* lens, uint32_t nsym, uint
     for (uint32_t l = 1; l <= 15; l++) {
       left = 2 * left - (int64_t)sh.count[l];
       used += sh.count[l];
-      if (left < 0) set_err(sh, kECODE);
+      if (left < 0) set_err(kECODE);
     }
-    if (used && left != 0) set_err(sh, kECODE);
-    if (!used && !is_dist) set_err(sh, kECODE);
+    if (used && left != 0) set_err(kECODE);
+    if (!used && !is_dist) set_err(kECODE);
     uint32_t code = 0;
-    sh.offs[1] = 0;
     sh.count[0] = 0;
     for (uint32_t l = 1; l <= 15; l++) {
       code = (code + sh.count[l - 1]) << 1;
       sh.first[l] = code;
-      sh.offs[l + 1] = sh.offs[l] + sh.count[l];
     }
-  }
-  __syncthreads();
-  // symbols in canonical order (by length, then symbol), ranks from ballots
-  if (t < 64) {
-    uint32_t run[16];
-#pragma unroll
-    for (int l = 0; l < 16; l++) run[l] = 0;
-    const uint64_t below = (1ull << t) - 1ull;
-    for (uint32_t c = 0; c < nsym; c += 64) {
-      uint32_t s = c + t;
-      uint32_t l = s < nsym ? lens[s] : 0;
-      uint32_t rank = 0;
-#pragma unroll
-      for (uint32_t q = 1; q <= 15; q++) {
-        uint64_t m = __ballot(l == q);
-        if (l == q) rank = run[q] + (uint32_t)__popcll(m & below);
-        run[q] += (uint32_t)__popcll(m);
-      }
-      if (l && l <= 15) sh.sorted[sh.offs[l] + rank] = (uint16_t)s;
-    }
+    sh.count[0] = used;
   }
   __syncthreads();
   if (sh.err) return;
   const uint32_t size = 1u << lmax;
-  for (uint32_t e = t; e < size; e += kThreads) {
-    uint32_t m = __builtin_bitreverse32(e) >> (32 - lmax);  // first stream bit = code MSB
-    uint32_t entry = 0;
-    for (uint32_t l = 1; l <= lmax; l++) {
-      uint32_t c = m >> (lmax - l);
-      uint32_t k = c - sh.first[l];
-      if (k < sh.count[l]) {
-        uint32_t sym = sh.sorted[sh.offs[l] + k];
-        uint32_t base, extra, kind;
-        if (is_dist) {
-          kind = kKindDist;
-          if (sym >= kNumD) break;
-          dist_code(sym, base, extra);
-        } else if (sym < 256) {
-          kind = kKindLit;
-          base = sym;
-          extra = 0;
-        } else if (sym == 256) {
-          kind = kKindEnd;
-          base = 0;
-          extra = 0;
-        } else {
-          kind = kKindLen;
-          length_code(sym - 257, base, extra);
-        }
-        uint32_t n = l;
-        if (l + extra <= lmax) {  // fold the extra bits into the entry
-          base += (e >> l) & ((1u << extra) - 1u);
-          n = l + extra;
-          extra = 0;
-        }
-        entry = n | (extra << 5) | (kind << 9) | (base << 16);
-        break;
-      }
+  if (sh.count[0] == 0) {
+    for (uint32_t e = t; e < size; e += kThreads) lut[e] = 0;  // no codes: every entry invalid
+    return;
+  }
+  uint32_t first[16];
+#pragma unroll
+  for (int l = 0; l < 16; l++) first[l] = sh.first[l];
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t run[16];
+#pragma unroll
+  for (int l = 0; l < 16; l++) run[l] = 0;
+  for (uint32_t c = 0, chunk = 0; c < nsym; c += 64, chunk++) {
+    const uint32_t s = c + lane;
+    const uint32_t l = s < nsym ? lens[s] : 0;
+    uint32_t code = 0;
+#pragma unroll
+    for (uint32_t q = 1; q <= 15; q++) {
+      const uint64_t m = __ballot(l == q);
+      if (l == q) code = first[q] + run[q] + (uint32_t)__popcll(m & below);
+      run[q] += (uint32_t)__popcll(m);
     }
-    lut[e] = entry;
+    if (chunk % kWaves != wave || l == 0) continue;
+    uint32_t base, extra, kind;
+    if (is_dist) {
+      kind = kKindDist;
+      dist_code(s < kNumD ? s : 0, base, extra);
+    } else if (s < 256) {
+      kind = kKindLit;
+      base = s;
+      extra = 0;
+    } else if (s == 256) {
+      kind = kKindEnd;
+      base = 0;
+      extra = 0;
+    } else {
+      kind = kKindLen;
+      length_code(s - 257, base, extra);
+    }
+    const uint32_t rev = __builtin_bitreverse32(code) >> (32 - l);  // first stream bit = code MSB
+    const bool fold = l + extra <= lmax;                             // extra bits inside the lookup
+    const uint32_t n = fold ? l + extra : l, x = fold ? 0 : extra;
+    const uint32_t emask = fold ? (1u << extra) - 1u : 0u;
+    for (uint32_t j = 0; j < (size >> l); j++)
+      lut[rev | (j << l)] = n | (x << 5) | (kind << 9) | ((base + (j & emask)) << 16);
   }
 }
 
 // ---------------------------------------------------------------- block scan
 template <int kThreads>
-__device__ __forceinline__ void block_excl_scan4(Shared& sh, uint32_t v[4], uint32_t tot[4]) {
+__device__ __forceinline__ void block_excl_scan4(uint32_t v[4], uint32_t tot[4]) {
+  Misc& sh = s_misc;
   constexpr int kW = kThreads / 64;
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t inc[4];
@@ -237,40 +301,103 @@ __device__ __forceinline__ void block_excl_scan4(Shared& sh, uint32_t v[4], uint
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- A2 fetch
+// Fetcher lane f feeds decoder lanes f, f+64, ...: it copies each lane's
+// sub-block into that lane's ring of kRows 16-byte rows (row slot r of all
+// lanes forms one contiguous 64-lane strip, so one copy instruction serves a
+// whole wavefront), never running more than the ring ahead of what the lane
+// has taken, and publishes how many words are present.
+template <int kDec>
+__device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
+  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  const uint32_t f = lane_id();
+  uint32_t total[kDec], woff[kDec], fetched[kDec];
+#pragma unroll
+  for (int v = 0; v < kDec; v++) {
+    total[v] = s_misc.sub_nw[f + 64 * v];
+    woff[v] = s_misc.sub_woff[f + 64 * v];
+    fetched[v] = 0;
+  }
+  for (;;) {
+    bool left = false, issued = false;
+    uint32_t limit[kDec];
+#pragma unroll
+    for (int v = 0; v < kDec; v++) {
+      const uint32_t rd = lds_acquire(&s_misc.rd[f + 64 * v]);
+      if (rd == kDone) fetched[v] = total[v];  // the lane stopped: nothing more to deliver
+      limit[v] = fetched[v] < total[v] ? min(total[v], (rd & ~3u) + 4 * kRows) : fetched[v];
+      left |= fetched[v] < total[v];
+    }
+    if (!__ballot(left)) break;
+#pragma unroll
+    for (int v = 0; v < kDec; v++) {
+      const uint32_t row0 = fetched[v] / 4, row1 = limit[v] / 4;
+      for (uint32_t r = 0; r < kRows; r++) {
+        const uint32_t a = row0 + ((r + kRows - row0 % kRows) % kRows);  // the lane's row held in slot r
+        const bool go = a < row1;
+        if (__ballot(go)) {
+          if (go) dma16(payload + 16ull * (woff[v] / 4 + a), &s_stage[r * kLanes + 64 * v]);
+          issued = true;
+        }
+      }
+    }
+    if (issued) {
+      wait_all_memory();
+#pragma unroll
+      for (int v = 0; v < kDec; v++) {
+        fetched[v] = limit[v];
+        lds_release(&s_misc.avail[f + 64 * v], fetched[v]);
+      }
+    } else {
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- A2 decode
 struct SubBlock {
-  const uint32_t* words;
   uint32_t n_words, bit_len;
   uint32_t n_seq, n_lit, raw_len, raw_off;
-  uint2* seq_out;
-  uint8_t* lit_out;
+  GMEM uint64_t* seq_out;  // records: literal length | (match length | distance << 16) << 32
+  GMEM uint8_t* lit_out;
 };
 
-// Decode one sub-block's bitstream: literal bytes to lit_out, one record per
-// sequence {literal length, match length | distance << 16} to seq_out.
-__device__ int decode_subblock(const SubBlock& sb, const uint32_t* __restrict__ lut_ll,
+// Decode one sub-block's bitstream (lane L of the decoder wavefronts): literal
+// bytes to lit_out, one record per sequence to seq_out.  The bit buffer holds
+// 33..64 bits at each lookup; stream words come from the lane's LDS ring, one
+// word read ahead.
+template <int kDec>
+__device__ int decode_subblock(const SubBlock& sb, uint32_t L, const uint32_t* __restrict__ lut_ll,
                                const uint32_t* __restrict__ lut_d, uint32_t lmax, uint32_t window,
                                uint32_t max_match) {
+  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
   if (sb.bit_len == 0) return kESUB;
   const uint32_t lmask = (1u << lmax) - 1u;
-  const uint32_t last = sb.n_words - 1;
-  const uint32_t* wp = sb.words;
-  // refill queue: words are requested four refills before they are used
-  uint64_t buf = (uint64_t)wp[0] | ((uint64_t)wp[min(1u, last)] << 32);
+  const uint32_t nw = sb.n_words;
+  uint32_t rd = 0, avail = 0;
+  auto pull = [&]() -> uint32_t {
+    if (rd >= nw) return 0u;  // past the end: padding, never consumed
+    while (rd >= avail) {
+      avail = lds_acquire(&s_misc.avail[L]);
+      if (rd >= avail) __builtin_amdgcn_s_sleep(1);
+    }
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(&s_stage[((rd >> 2) % kRows) * kLanes + L]);
+    const uint32_t w = row[rd & 3];
+    rd++;
+    s_misc.rd[L] = rd;
+    return w;
+  };
+  uint64_t buf = pull();
+  buf |= (uint64_t)pull() << 32;
   uint32_t nb = 64;
-  uint32_t q0 = wp[min(2u, last)], q1 = wp[min(3u, last)], q2 = wp[min(4u, last)], q3 = wp[min(5u, last)];
-  uint32_t next = 6;
-#define GMP_REFILL()                                   \
-  do {                                                 \
-    if (nb <= 32) {                                    \
-      buf |= (uint64_t)q0 << nb;                       \
-      nb += 32;                                        \
-      q0 = q1;                                         \
-      q1 = q2;                                         \
-      q2 = q3;                                         \
-      q3 = wp[min(next, last)];                        \
-      next++;                                          \
-    }                                                  \
+  uint32_t next = pull();
+#define GMP_REFILL()                    \
+  do {                                  \
+    if (nb <= 32) {                     \
+      buf |= (uint64_t)next << nb;      \
+      nb += 32;                         \
+      next = pull();                    \
+    }                                   \
   } while (0)
 
   uint32_t used = 0, produced = 0, sc = 0, lc = 0, run = 0;
@@ -305,13 +432,13 @@ __device__ int decode_subblock(const SubBlock& sb, const uint32_t* __restrict__ 
       if (val > max_match) return kELEN;
       if (dist > window || dist > sb.raw_off + produced) return kEDIST;
       if (sc >= sb.n_seq) return kESUB;
-      sb.seq_out[sc++] = make_uint2(run, val | (dist << 16));
+      sb.seq_out[sc++] = (uint64_t)run | ((uint64_t)(val | (dist << 16)) << 32);
       run = 0;
       produced += val;
     } else if (kind == kKindEnd) {
       if (run) {
         if (sc >= sb.n_seq) return kESUB;
-        sb.seq_out[sc++] = make_uint2(run, 0u);
+        sb.seq_out[sc++] = (uint64_t)run;
       }
       if (used != sb.bit_len || sc != sb.n_seq || lc != sb.n_lit || produced != sb.raw_len) return kESUB;
       return kOK;
@@ -398,24 +525,37 @@ __device__ __forceinline__ void copy_match(uint8_t* ring, uint32_t dst, uint32_t
   for (uint32_t k = p16; k < len; k += p16) ring_write(ring, dst + k, v, min(16u, len - k));
 }
 
-__device__ __forceinline__ uint4 gload16(const uint8_t* p) {
+__device__ __forceinline__ uint4 lit_read16(uint32_t p) {
+  const uint8_t* r = lit_ring();
+  const uint32_t a = p & (kLitRing - 1);
   uint4 v;
-  __builtin_memcpy(&v, p, 16);
+  if (a <= kLitRing - 16) {
+    __builtin_memcpy(&v, r + a, 16);
+  } else {
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; i++) {
+      lo |= (uint64_t)r[(p + i) & (kLitRing - 1)] << (8 * i);
+      hi |= (uint64_t)r[(p + 8 + i) & (kLitRing - 1)] << (8 * i);
+    }
+    v = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+  }
   return v;
 }
 
-// Flush window bytes [flushed, upto) to HBM: whole 16-byte chunks once a
-// full 1 KiB is pending, everything when final.
-__device__ __forceinline__ void flush_window(const uint8_t* ring, uint8_t* out, uint32_t& flushed, uint32_t upto,
-                                             bool final_flush, uint32_t lane, uint32_t raw_len) {
+// Flush window bytes [flushed, upto) to HBM: whole 16-byte chunks once at
+// least 1 KiB is pending (and everything when final).
+__device__ __forceinline__ void flush_window(GMEM uint8_t* out, uint32_t& flushed, uint32_t upto, bool final_flush,
+                                             uint32_t lane, uint32_t raw_len) {
+  const uint8_t* ring = ring_ptr();
   upto = min(upto, raw_len);  // never past the block's output
-  if (!final_flush && upto - flushed < kFlushChunk) return;
+  if (!final_flush && upto - flushed < 1024) return;
   const uint32_t end = final_flush ? upto : (upto & ~15u);
-  for (uint32_t p = flushed + lane * 16; p < end; p += kFlushChunk) {
+  for (uint32_t p = flushed + lane * 16; p < end; p += 1024) {
     if (p + 16 <= end) {
       uint4 v;
       __builtin_memcpy(&v, ring + (p & kRingMask), 16);
-      __builtin_memcpy(out + p, &v, 16);
+      gstore16(out + p, v);
     } else {
       for (uint32_t q = p; q < end; q++) out[q] = ring[q & kRingMask];
     }
@@ -423,37 +563,103 @@ __device__ __forceinline__ void flush_window(const uint8_t* ring, uint8_t* out, 
   flushed = end;
 }
 
+// Rare paths that read literal bytes straight from HBM (literal groups larger
+// than the staging ring, literal runs longer than the window).  They are kept
+// out of line so that their loads never merge with the registers of the LDS
+// path: a merge would make the resolver wait for its own output stores.
+__device__ __noinline__ void copy_lits_hbm(const GMEM uint8_t* src, uint32_t pos, uint32_t len) {
+  uint8_t* ring = ring_ptr();
+  for (uint32_t k = 0; k < len; k += 16) ring_write(ring, pos + k, gload16(src + k), min(16u, len - k));
+}
+// All lanes together copy n literal bytes from src to window position base.
+__device__ __noinline__ void stream_lits_hbm(const GMEM uint8_t* src, uint32_t base, uint32_t n, uint32_t lane) {
+  uint8_t* ring = ring_ptr();
+  for (uint32_t k = lane * 16; k < n; k += 1024) ring_write(ring, base + k, gload16(src + k), min(16u, n - k));
+}
+
 // ---------------------------------------------------------------- A3-A6
 struct LzArgs {
-  const uint2* seqs;
-  const uint8_t* lits;
-  uint8_t* out;
-  uint32_t n_seq, raw_len;
+  const GMEM uint8_t* ws;  // token workspace: records, then literal bytes
+  uint64_t ws_len;
+  GMEM uint8_t* out;
+  uint32_t n_seq, n_lit, raw_len;
   bool single_pass;
-  uint8_t* rounds;
+  GMEM uint8_t* rounds;
 };
 
-__device__ void resolve_block(uint8_t* ring, const LzArgs& a) {
+// Fetcher side of A3-A6: stream records (1 KiB = 128 records per copy) and
+// literal bytes (1 KiB per copy) into their LDS rings, at most one ring ahead
+// of what the resolver has consumed.
+__device__ void fetch_tokens(const LzArgs& a) {
   const uint32_t lane = lane_id();
+  const uint32_t rec_chunks = (a.n_seq + 127) / 128, lit_chunks = (a.n_lit + 1023) / 1024;
+  const uint64_t lit_base = 8ull * a.n_seq;
+  uint32_t rf = 0, lf = 0;
+  while (rf < rec_chunks || lf < lit_chunks) {
+    const uint32_t rc = lds_acquire(&s_misc.rec_cons), lc = lds_acquire(&s_misc.lit_cons);
+    if (rc == kDone && lc == kDone) break;  // the resolver has finished
+    uint32_t issued = 0;
+    while (rf < rec_chunks && (rc == kDone || 128 * (rf + 1) <= rc + kRecRing) && issued < 8) {
+      uint64_t o = 1024ull * rf + 16 * lane;
+      if (o + 16 > a.ws_len) o = a.ws_len - 16;
+      dma16(a.ws + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
+      rf++;
+      issued++;
+    }
+    while (lf < lit_chunks && (lc == kDone || 1024 * (lf + 1) <= lc + kLitRing) && issued < 12) {
+      uint64_t o = lit_base + 1024ull * lf + 16 * lane;
+      if (o + 16 > a.ws_len) o = a.ws_len - 16;
+      dma16(a.ws + o, &lit_ring()[1024 * (lf % (kLitRing / 1024))]);
+      lf++;
+      issued++;
+    }
+    if (issued) {
+      wait_all_memory();
+      lds_release(&s_misc.lit_avail, min(a.n_lit, 1024 * lf));
+      lds_release(&s_misc.rec_avail, min(a.n_seq, 128 * rf));
+    } else {
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+}
+
+// Resolver: groups of 64 sequences, one per lane.
+__device__ void resolve_block(const LzArgs& a) {
+  uint8_t* ring = ring_ptr();
+  const uint32_t lane = lane_id();
+  const GMEM uint8_t* lits = a.ws + 8ull * a.n_seq;
   uint32_t carry_lit = 0, carry_out = 0, flushed = 0;
-  uint32_t g = 0;
-  uint2 rec_next = make_uint2(0u, 0u);
-  if (lane < a.n_seq) rec_next = a.seqs[lane];
-  for (uint32_t g0 = 0; g0 < a.n_seq; g0 += 64, g++) {
+  uint32_t rec_avail = 0, lit_avail = 0;
+  const uint32_t n_groups = (a.n_seq + 63) / 64;
+  for (uint32_t g = 0; g < n_groups; g++) {
+    const uint32_t g0 = g * 64;
+    const uint32_t need = min(a.n_seq, g0 + 64);
+    while (rec_avail < need) {
+      rec_avail = lds_acquire(&s_misc.rec_avail);
+      if (rec_avail < need) __builtin_amdgcn_s_sleep(1);
+    }
     const uint32_t j = g0 + lane;
     const bool valid = j < a.n_seq;
-    uint2 rec = rec_next;
-    if (g0 + 64 + lane < a.n_seq) rec_next = a.seqs[g0 + 64 + lane];  // next group's records
-    uint32_t L = valid ? rec.x : 0u;
-    const uint32_t M = valid ? (rec.y & 0xFFFFu) : 0u;
-    const uint32_t D = valid ? (rec.y >> 16) : 0u;
+    const uint2 rec = valid ? rec_ring()[j % kRecRing] : make_uint2(0u, 0u);
+    uint32_t L = rec.x;
+    const uint32_t M = rec.y & 0xFFFFu;
+    const uint32_t D = rec.y >> 16;
     // A3: two exclusive prefix sums over the group's sequences
     const uint32_t inc_lit = wave_incl_scan(L);
     const uint32_t inc_out = wave_incl_scan(L + M);
+    const uint32_t tot_lit = readlane(inc_lit, 63);
     uint32_t lsrc = carry_lit + inc_lit - L;
     uint32_t pos = carry_out + inc_out - (L + M);
     const uint32_t end = pos + L + M;
     const uint32_t m_cnt = min(64u, a.n_seq - g0);
+    // literals come from the LDS ring unless the group holds more than half of it
+    const bool lits_staged = tot_lit <= kLitStagedMax;
+    if (lits_staged && tot_lit) {
+      while (lit_avail < carry_lit + tot_lit) {
+        lit_avail = lds_acquire(&s_misc.lit_avail);
+        if (lit_avail < carry_lit + tot_lit) __builtin_amdgcn_s_sleep(1);
+      }
+    }
     uint32_t rounds = 0;
     bool split = false;
     uint32_t lo = 0;
@@ -464,9 +670,8 @@ __device__ void resolve_block(uint8_t* ring, const LzArgs& a) {
         uint32_t Llo = readlane(L, lo), Mlo = readlane(M, lo), slo = readlane(lsrc, lo);
         while (Llo + Mlo > kSpanCap) {
           const uint32_t P = kSpanCap / 2;
-          for (uint32_t k = lane * 16; k < P; k += 1024)
-            ring_write(ring, base + k, gload16(a.lits + slo + k), min(16u, P - k));
-          flush_window(ring, a.out, flushed, base + P, false, lane, a.raw_len);
+          stream_lits_hbm(lits + slo, base, P, lane);
+          flush_window(a.out, flushed, base + P, false, lane, a.raw_len);
           base += P;
           slo += P;
           Llo -= P;
@@ -483,8 +688,13 @@ __device__ void resolve_block(uint8_t* ring, const LzArgs& a) {
       if (hi < m_cnt) split = true;
       const bool active = lane >= lo && lane < hi;
       // A4: literal strings into the window
-      if (active)
-        for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, gload16(a.lits + lsrc + k), min(16u, L - k));
+      if (active && L) {
+        if (lits_staged) {
+          for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
+        } else {
+          copy_lits_hbm(lits + lsrc, pos, L);
+        }
+      }
       const uint32_t dst = pos + L;
       bool pending = active && M > 0;
       if (a.single_pass) {
@@ -505,31 +715,38 @@ __device__ void resolve_block(uint8_t* ring, const LzArgs& a) {
           rounds++;
         }
       }
-      const uint32_t sub_end = readlane(end, hi - 1);
-      flush_window(ring, a.out, flushed, sub_end, false, lane, a.raw_len);
+      flush_window(a.out, flushed, readlane(end, hi - 1), false, lane, a.raw_len);
       lo = hi;
     }
     if (a.rounds && lane == 0) a.rounds[g] = (uint8_t)(min(rounds, 127u) | (split ? 0x80u : 0u));
-    carry_lit += readlane(inc_lit, 63);
+    carry_lit += tot_lit;
     carry_out += readlane(inc_out, 63);
+    lds_release(&s_misc.lit_cons, carry_lit);
+    lds_release(&s_misc.rec_cons, min(a.n_seq, g0 + 64));
   }
-  flush_window(ring, a.out, flushed, a.raw_len, true, lane, a.raw_len);
+  flush_window(a.out, flushed, a.raw_len, true, lane, a.raw_len);
+  lds_release(&s_misc.lit_cons, kDone);
+  lds_release(&s_misc.rec_cons, kDone);
 }
 
 // ---------------------------------------------------------------- kernel
-__device__ __forceinline__ uint32_t ld32(const uint8_t* p) {
-  uint32_t v;
-  __builtin_memcpy(&v, p, 4);
-  return v;
+__device__ __forceinline__ uint32_t ld32(const GMEM uint8_t* p) { return gload32(p); }
+
+__device__ __forceinline__ void stamp(const DevJob& job, int i) {
+  if (job.times && threadIdx.x == 0) gmem(job.times)[i] = wall_clock64();
 }
 
 // kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR or GMPK_MODE_DE.
-template <int kThreads, int kMode>
-__device__ void inflate_block(Shared& sh, const DevJob& job, uint32_t flags) {
-  const uint32_t t = threadIdx.x;
+template <int kDec, int kMode>
+__device__ void inflate_block(const DevJob& job, uint32_t flags) {
+  constexpr uint32_t kThreads = 64 * (kDec + 1), kLanes = 64 * kDec;
+  Misc& sh = s_misc;
+  const uint32_t t = threadIdx.x, wave = t >> 6;
+  stamp(job, 0);
   if (t == 0) sh.err = 0;
   __syncthreads();
-  const uint8_t* blk = job.comp;
+  const GMEM uint8_t* blk = gmem(job.comp);
+  GMEM int32_t* status = gmem(job.status);
   // ---- A0: header
   int err = kOK;
   uint32_t mode = 0, group = 0, lmax = 0, raw_len = 0, window = 0, max_match = 0, n_sub = 0, n_seq = 0,
@@ -557,8 +774,9 @@ __device__ void inflate_block(Shared& sh, const DevJob& job, uint32_t flags) {
       err = kEFORMAT;
     } else {
       payload = ld32(blk + kHdrBytes + kIdxBytes * n_sub);
-      if ((uint64_t)kHdrBytes + (uint64_t)kIdxBytes * n_sub + 16 + payload > job.comp_len) err = kEFORMAT;
-      else if (n_seq != job.n_seq || n_lit != job.n_lit) err = kEFORMAT;
+      if ((uint64_t)kHdrBytes + (uint64_t)kIdxBytes * n_sub + 16 + payload > job.comp_len || (payload & 15))
+        err = kEFORMAT;
+      else if (n_seq != job.n_seq || n_lit != job.n_lit || job.ws_len < 8ull * n_seq + n_lit + 64) err = kEFORMAT;
       else if (raw_len != job.out_len) err = kESIZE;
     }
   }
@@ -566,123 +784,143 @@ __device__ void inflate_block(Shared& sh, const DevJob& job, uint32_t flags) {
   if (err == kOK && kMode == GMPK_MODE_DE && !de_ok) err = kEINVAL;
   const bool single_pass = (kMode == GMPK_MODE_DE) || (kMode == GMPK_MODE_AUTO && de_ok);
   if (err != kOK) {
-    if (t == 0) *job.status = err;
+    if (t == 0) *status = err;
     return;
   }
   if (n_sub == 0) {
     // an empty block: nothing to decode
-    if (t == 0) *job.status = (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kOK : kEFORMAT;
+    if (t == 0) *status = (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kOK : kEFORMAT;
     return;
   }
   // ---- A1: code lengths and lookup tables
   for (uint32_t i = t; i < kNumLL + kNumD; i += kThreads) sh.lens[i] = (blk[32 + i / 2] >> ((i & 1) * 4)) & 15;
   __syncthreads();
-  if (sh.lens[256] == 0) set_err(sh, kECODE);
-  uint32_t* lut_ll = sh.lut;
-  uint32_t* lut_d = sh.lut + kLutSize;
-  build_table<kThreads>(sh, sh.lens, kNumLL, lmax, lut_ll, false);
+  if (sh.lens[256] == 0) set_err(kECODE);
+  uint32_t* lut_ll = s_big;
+  uint32_t* lut_d = s_big + kLutSize;
+  build_table<kThreads>(sh.lens, kNumLL, lmax, lut_ll, false);
   __syncthreads();
-  build_table<kThreads>(sh, sh.lens + kNumLL, kNumD, lmax, lut_d, true);
+  build_table<kThreads>(sh.lens + kNumLL, kNumD, lmax, lut_d, true);
   __syncthreads();
   if (sh.err) {
-    if (t == 0) *job.status = sh.err;
+    if (t == 0) *status = sh.err;
     return;
   }
+  stamp(job, 1);
   // ---- A0/A2: sub-block offsets by prefix sums over the index, then decode
-  const uint8_t* idx = blk + kHdrBytes;
-  const uint32_t* payload_words = reinterpret_cast<const uint32_t*>(blk + kHdrBytes + kIdxBytes * n_sub + 16);
-  uint2* ws_seq = reinterpret_cast<uint2*>(job.ws);
-  uint8_t* ws_lit = job.ws + 8ull * n_seq;
+  const GMEM uint8_t* idx = blk + kHdrBytes;
+  const GMEM uint8_t* payload_bytes = blk + kHdrBytes + kIdxBytes * n_sub + 16;
+  GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
+  GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
   uint32_t carry[4] = {0, 0, 0, 0};
-  for (uint32_t c = 0; c < n_sub; c += kThreads) {
+  for (uint32_t c = 0; c < n_sub; c += kLanes) {
     const uint32_t s = c + t;
+    const bool mine = t < kLanes && s < n_sub;
     uint32_t bit_len = 0, sseq = 0, slit = 0, sraw = 0;
-    if (s < n_sub) {
-      uint4 e;
-      __builtin_memcpy(&e, idx + kIdxBytes * s, 16);
+    if (mine) {
+      const uint4 e = gload16(idx + kIdxBytes * s);
       bit_len = e.x;
       sseq = e.y;
       slit = e.z;
       sraw = e.w;
     }
-    const uint32_t nwords = (uint32_t)(((uint64_t)bit_len + 31) >> 5);
+    const uint32_t nwords = (uint32_t)((((uint64_t)bit_len + 127) >> 7) << 2);  // padded to 16 bytes
     uint32_t v[4] = {nwords, sseq, slit, sraw}, tot[4];
-    block_excl_scan4<kThreads>(sh, v, tot);
+    block_excl_scan4<kThreads>(v, tot);
     // offsets may wrap for corrupt indexes; the sums are checked below
     const uint32_t word_off = carry[0] + v[0], seq_off = carry[1] + v[1], lit_off = carry[2] + v[2],
                    raw_off = carry[3] + v[3];
 #pragma unroll
     for (int i = 0; i < 4; i++) carry[i] += tot[i];
-    if (s < n_sub) {
-      int e = kOK;
-      const uint64_t words_end = (uint64_t)word_off + nwords;
-      if (words_end * 4 > payload || (uint64_t)seq_off + sseq > n_seq || (uint64_t)lit_off + slit > n_lit ||
-          (uint64_t)raw_off + sraw > raw_len) {
-        e = kEFORMAT;
-      } else {
-        SubBlock sb;
-        sb.words = payload_words + word_off;
-        sb.n_words = nwords;
-        sb.bit_len = bit_len;
-        sb.n_seq = sseq;
-        sb.n_lit = slit;
-        sb.raw_len = sraw;
-        sb.raw_off = raw_off;
-        sb.seq_out = ws_seq + seq_off;
-        sb.lit_out = ws_lit + lit_off;
-        e = decode_subblock(sb, lut_ll, lut_d, lmax, window, max_match);
-      }
-      if (e != kOK) set_err(sh, e);
+    bool ok = false;
+    if (t < kLanes) {
+      ok = mine && (uint64_t)word_off + nwords <= payload / 4 && (uint64_t)seq_off + sseq <= n_seq &&
+           (uint64_t)lit_off + slit <= n_lit && (uint64_t)raw_off + sraw <= raw_len;
+      if (mine && !ok) set_err(kEFORMAT);
+      sh.sub_woff[t] = word_off;
+      sh.sub_nw[t] = ok ? nwords : 0;
+      sh.rd[t] = ok ? 0 : kDone;
+      sh.avail[t] = 0;
     }
+    __syncthreads();
+    if (wave == kDec) {
+      fetch_bitstreams<kDec>(payload_bytes);
+    } else if (ok) {
+      SubBlock sb;
+      sb.n_words = nwords;
+      sb.bit_len = bit_len;
+      sb.n_seq = sseq;
+      sb.n_lit = slit;
+      sb.raw_len = sraw;
+      sb.raw_off = raw_off;
+      sb.seq_out = ws_seq + seq_off;
+      sb.lit_out = ws_lit + lit_off;
+      const int e = decode_subblock<kDec>(sb, t, lut_ll, lut_d, lmax, window, max_match);
+      lds_release(&sh.rd[t], kDone);
+      if (e != kOK) set_err(e);
+    }
+    __syncthreads();
   }
   // the index must account for the whole payload and the header counts
   if (t == 0 && (carry[0] * 4ull != payload || carry[1] != n_seq || carry[2] != n_lit || carry[3] != raw_len))
-    set_err(sh, kEFORMAT);
+    set_err(kEFORMAT);
   __syncthreads();  // workspace writes of all lanes are visible after this barrier
   if (sh.err) {
-    if (t == 0) *job.status = sh.err;
+    if (t == 0) *status = sh.err;
     return;
   }
-  if (t >= 64) return;
-  // ---- A3-A6 on wavefront 0
+  stamp(job, 2);
+  // ---- A3-A6: decoder wavefront 0 resolves, the fetcher stages tokens
   LzArgs a;
-  a.seqs = ws_seq;
-  a.lits = ws_lit;
-  a.out = job.out;
+  a.ws = gmem(job.ws);
+  a.ws_len = job.ws_len;
+  a.out = gmem(job.out);
   a.n_seq = n_seq;
+  a.n_lit = n_lit;
   a.raw_len = raw_len;
   a.single_pass = single_pass;
-  a.rounds = (flags & GMPK_FLAG_STATS) ? job.rounds : nullptr;
-  resolve_block(sh.ring, a);
-  if (t == 0) *job.status = kOK;
+  a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
+  if (t == 0) {
+    sh.rec_avail = 0;
+    sh.lit_avail = 0;
+    sh.rec_cons = 0;
+    sh.lit_cons = 0;
+  }
+  __syncthreads();
+  if (wave == kDec) {
+    fetch_tokens(a);
+  } else if (wave == 0) {
+    resolve_block(a);
+    stamp(job, 3);
+    if (t == 0) *status = kOK;
+  }
 }
 
-template <int kThreads, int kMode>
-__global__ __launch_bounds__(kThreads) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
-                                                           uint32_t flags) {
-  __shared__ Shared sh;
+template <int kDec, int kMode>
+__global__ __launch_bounds__(64 * (kDec + 1)) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
+                                                                  uint32_t flags) {
   if (blockIdx.x >= n_jobs) return;
-  const DevJob job = jobs[blockIdx.x];
-  inflate_block<kThreads, kMode>(sh, job, flags);
+  DevJob job = jobs[blockIdx.x];
+  if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
+  inflate_block<kDec, kMode>(job, flags);
 }
 
 // Persistent form: workgroups take block indices from a device counter until
 // the job table is exhausted; every workgroup exits once it draws an index
 // past the end.
-template <int kThreads, int kMode>
-__global__ __launch_bounds__(kThreads) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
-                                                                      uint32_t n_jobs, uint32_t flags,
-                                                                      uint32_t* __restrict__ queue) {
-  __shared__ Shared sh;
-  __shared__ uint32_t next;
+template <int kDec, int kMode>
+__global__ __launch_bounds__(64 * (kDec + 1)) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
+                                                                             uint32_t n_jobs, uint32_t flags,
+                                                                             uint32_t* __restrict__ queue) {
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) s_misc.next_job = atomicAdd(queue, 1u);
     __syncthreads();
-    const uint32_t j = next;
+    const uint32_t j = s_misc.next_job;
     __syncthreads();
     if (j >= n_jobs) return;
-    const DevJob job = jobs[j];
-    inflate_block<kThreads, kMode>(sh, job, flags);
+    DevJob job = jobs[j];
+    if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
+    inflate_block<kDec, kMode>(job, flags);
     __syncthreads();
   }
 }
@@ -690,47 +928,42 @@ __global__ __launch_bounds__(kThreads) void inflate_persistent_kernel(const DevJ
 // resets the persistent queue head (a kernel, so that graph captures hold no memset node)
 __global__ void reset_queue_kernel(uint32_t* queue) { *queue = 0; }
 
-}  // namespace gmpk
-
-namespace gmpk {
-
-template <int kThreads, int kMode>
+template <int kDec, int kMode>
 void launch_one(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t persistent, uint32_t workgroups,
                 uint32_t* d_queue, hipStream_t stream) {
   if (persistent) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, d_queue);
-    hipLaunchKernelGGL((inflate_persistent_kernel<kThreads, kMode>), dim3(workgroups), dim3(kThreads), 0, stream,
+    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(64 * (kDec + 1)), 0, stream,
                        d_jobs, n_jobs, flags, d_queue);
   } else {
-    hipLaunchKernelGGL((inflate_kernel<kThreads, kMode>), dim3(n_jobs), dim3(kThreads), 0, stream, d_jobs, n_jobs,
+    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(64 * (kDec + 1)), 0, stream, d_jobs, n_jobs,
                        flags);
   }
 }
 
-template <int kThreads>
+template <int kDec>
 int launch_mode(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t persistent, uint32_t workgroups,
                 uint32_t* d_queue, hipStream_t stream) {
   switch (flags & GMPK_MODE_MASK) {
-    case GMPK_MODE_AUTO: launch_one<kThreads, GMPK_MODE_AUTO>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
-    case GMPK_MODE_MRR: launch_one<kThreads, GMPK_MODE_MRR>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
-    case GMPK_MODE_DE: launch_one<kThreads, GMPK_MODE_DE>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
+    case GMPK_MODE_AUTO: launch_one<kDec, GMPK_MODE_AUTO>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
+    case GMPK_MODE_MRR: launch_one<kDec, GMPK_MODE_MRR>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
+    case GMPK_MODE_DE: launch_one<kDec, GMPK_MODE_DE>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
     default: return -1;
   }
 }
 
 }  // namespace gmpk
 
-extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t waves,
+extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t dec_waves,
                            uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, hipStream_t stream) {
   using namespace gmpk;
   if (n_jobs == 0) return 0;
   if (persistent && workgroups == 0) return -1;
   int rc;
-  switch (waves) {
-    case 1: rc = launch_mode<64>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 2: rc = launch_mode<128>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 4: rc = launch_mode<256>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 8: rc = launch_mode<512>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
+  switch (dec_waves) {
+    case 1: rc = launch_mode<1>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
+    case 2: rc = launch_mode<2>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
+    case 4: rc = launch_mode<4>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
     default: return -1;
   }
   if (rc) return rc;
