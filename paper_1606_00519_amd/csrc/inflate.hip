@@ -363,90 +363,92 @@ struct SubBlock {
 };
 
 // Decode one sub-block's bitstream (lane L of the decoder wavefronts): literal
-// bytes to lit_out, one record per sequence to seq_out.  The bit buffer holds
-// 33..64 bits at each lookup; stream words come from the lane's LDS ring, one
-// word read ahead.
+// bytes to lit_out, one record per sequence to seq_out.
+//
+// One symbol per step, from either table: a step in the literal/length state
+// looks up lut_ll, a step in the distance state lut_d (the two tables are
+// adjacent in LDS, so the state is just an index offset).  The stream is seen
+// through a window of words w0..w2 at bit offset s (0..31), so every step has
+// 64 fresh bits; the window slides by selects, w3 being the word after it and
+// nx the word after that, read from the lane's LDS ring a step before it is
+// needed.  The step is branch-free apart from the two stores and a stall path
+// that is taken only when the fetcher is behind; errors end the lane's loop.
 template <int kDec>
-__device__ int decode_subblock(const SubBlock& sb, uint32_t L, const uint32_t* __restrict__ lut_ll,
-                               const uint32_t* __restrict__ lut_d, uint32_t lmax, uint32_t window,
-                               uint32_t max_match) {
+__device__ int decode_subblock(const SubBlock& sb, uint32_t L, uint32_t lmax, uint32_t window, uint32_t max_match) {
   constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  static_assert((kRows & (kRows - 1)) == 0, "ring rows must be a power of two");
   if (sb.bit_len == 0) return kESUB;
   const uint32_t lmask = (1u << lmax) - 1u;
   const uint32_t nw = sb.n_words;
-  uint32_t rd = 0, avail = 0;
-  auto pull = [&]() -> uint32_t {
-    if (rd >= nw) return 0u;  // past the end: padding, never consumed
-    while (rd >= avail) {
-      avail = lds_acquire(&s_misc.avail[L]);
-      if (rd >= avail) __builtin_amdgcn_s_sleep(1);
-    }
-    const uint32_t* row = reinterpret_cast<const uint32_t*>(&s_stage[((rd >> 2) % kRows) * kLanes + L]);
-    const uint32_t w = row[rd & 3];
-    rd++;
-    s_misc.rd[L] = rd;
-    return w;
-  };
-  uint64_t buf = pull();
-  buf |= (uint64_t)pull() << 32;
-  uint32_t nb = 64;
-  uint32_t next = pull();
-#define GMP_REFILL()                    \
-  do {                                  \
-    if (nb <= 32) {                     \
-      buf |= (uint64_t)next << nb;      \
-      nb += 32;                         \
-      next = pull();                    \
-    }                                   \
-  } while (0)
-
-  uint32_t used = 0, produced = 0, sc = 0, lc = 0, run = 0;
-  for (;;) {
-    GMP_REFILL();
-    const uint32_t e = lut_ll[(uint32_t)buf & lmask];
-    const uint32_t n = e & 31u, x = (e >> 5) & 15u;
-    const uint32_t val = (e >> 16) + ((uint32_t)(buf >> n) & ((1u << x) - 1u));
-    const uint32_t tb = n + x;
-    buf >>= tb;
-    nb -= tb;
-    used += tb;
-    if (n == 0) return kECODE;
-    if (used > sb.bit_len) return kESUB;
-    const uint32_t kind = (e >> 9) & 3u;
-    if (kind == kKindLit) {
-      if (lc >= sb.n_lit) return kESUB;
-      sb.lit_out[lc++] = (uint8_t)val;
-      run++;
-      produced++;
-    } else if (kind == kKindLen) {
-      GMP_REFILL();
-      const uint32_t d = lut_d[(uint32_t)buf & lmask];
-      const uint32_t dn = d & 31u, dx = (d >> 5) & 15u;
-      const uint32_t dist = (d >> 16) + ((uint32_t)(buf >> dn) & ((1u << dx) - 1u));
-      const uint32_t tdb = dn + dx;
-      buf >>= tdb;
-      nb -= tdb;
-      used += tdb;
-      if (dn == 0) return kECODE;
-      if (used > sb.bit_len) return kESUB;
-      if (val > max_match) return kELEN;
-      if (dist > window || dist > sb.raw_off + produced) return kEDIST;
-      if (sc >= sb.n_seq) return kESUB;
-      sb.seq_out[sc++] = (uint64_t)run | ((uint64_t)(val | (dist << 16)) << 32);
-      run = 0;
-      produced += val;
-    } else if (kind == kKindEnd) {
-      if (run) {
-        if (sc >= sb.n_seq) return kESUB;
-        sb.seq_out[sc++] = (uint64_t)run;
+  const uint32_t* ring_base = reinterpret_cast<const uint32_t*>(s_stage) + 4 * L;
+  uint32_t avail = 0;
+  // word k of the lane's stream (zero past its end); waits for the fetcher when needed
+  auto ring_word = [&](uint32_t k) -> uint32_t {
+    if (k < nw && k >= avail) {
+      for (;;) {
+        avail = lds_acquire(&s_misc.avail[L]);
+        if (k < avail) break;
+        __builtin_amdgcn_s_sleep(1);
       }
-      if (used != sb.bit_len || sc != sb.n_seq || lc != sb.n_lit || produced != sb.raw_len) return kESUB;
-      return kOK;
-    } else {
-      return kECODE;
     }
+    const uint32_t w = ring_base[((k >> 2) & (kRows - 1)) * (4 * kLanes) + (k & 3)];
+    return k < nw ? w : 0u;
+  };
+  uint32_t w0 = ring_word(0), w1 = ring_word(1), w2 = ring_word(2), w3 = ring_word(3), nx = ring_word(4);
+  uint32_t rd = 4;  // index of the word in nx
+  uint32_t s = 0, pos = 0, state = 0;
+  uint32_t plen = 0, produced = 0, sc = 0, lc = 0, run = 0;
+  int ecode = kOK;
+  for (;;) {
+    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, s), hi = __builtin_amdgcn_alignbit(w2, w1, s);
+    const uint32_t e = s_big[(state << kLutBits) | (lo & lmask)];
+    const uint32_t n = e & 31u, x = (e >> 5) & 15u, kind = (e >> 9) & 3u;
+    const uint32_t val = (e >> 16) + __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi, lo, n), 0, x);
+    const uint32_t t = n + x;
+    pos += t;
+    s += t;
+    // slide the window by a word when s crossed 32 (t <= 26 and s < 32: at most one word)
+    const bool sh = s >= 32;
+    s &= 31;
+    w0 = sh ? w1 : w0;
+    w1 = sh ? w2 : w1;
+    w2 = sh ? w3 : w2;
+    w3 = sh ? nx : w3;
+    rd += sh ? 1u : 0u;
+    nx = ring_word(rd);
+    s_misc.rd[L] = rd - 4;  // words below rd-4 are out of the window: their ring slots are free
+    // what the symbol was
+    const bool is_dist = state != 0;
+    const bool is_lit = !is_dist && kind == kKindLit;
+    const bool is_len = !is_dist && kind == kKindLen;
+    const bool is_end = !is_dist && kind == kKindEnd;
+    const uint32_t lim = min(window, sb.raw_off + produced);
+    int code = n == 0 ? kECODE : kOK;
+    code = (code == kOK && is_dist && plen > max_match) ? kELEN : code;
+    code = (code == kOK && is_dist && val > lim) ? kEDIST : code;
+    code = (code == kOK && ((is_dist && sc >= sb.n_seq) || (is_lit && lc >= sb.n_lit) || pos > sb.bit_len)) ? kESUB
+                                                                                                         : code;
+    if (is_dist && code == kOK) sb.seq_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+    if (is_lit && code == kOK) sb.lit_out[lc] = (uint8_t)val;
+    sc += is_dist ? 1u : 0u;
+    lc += is_lit ? 1u : 0u;
+    produced += is_dist ? plen : (is_lit ? 1u : 0u);
+    run = is_dist ? 0u : run + (is_lit ? 1u : 0u);
+    plen = is_len ? val : plen;
+    state = is_len ? 1u : 0u;
+    if (code != kOK) {
+      ecode = code;
+      break;
+    }
+    if (is_end) break;
   }
-#undef GMP_REFILL
+  if (ecode != kOK) return ecode;
+  if (run) {
+    if (sc >= sb.n_seq) return kESUB;
+    sb.seq_out[sc++] = (uint64_t)run;
+  }
+  if (pos != sb.bit_len || sc != sb.n_seq || lc != sb.n_lit || produced != sb.raw_len) return kESUB;
+  return kOK;
 }
 
 // ---------------------------------------------------------------- ring helpers
@@ -563,6 +565,44 @@ __device__ __forceinline__ void flush_window(GMEM uint8_t* out, uint32_t& flushe
   flushed = end;
 }
 
+// Window/ring accesses that are known not to wrap (the common case).
+__device__ __forceinline__ void write_upto16(uint8_t* d, uint4 v, uint32_t n) {
+  if (n == 16) {
+    __builtin_memcpy(d, &v, 16);
+    return;
+  }
+  uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32), hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+  if (n & 8) {
+    __builtin_memcpy(d, &lo, 8);
+    d += 8;
+    lo = hi;
+  }
+  if (n & 4) {
+    const uint32_t w = (uint32_t)lo;
+    __builtin_memcpy(d, &w, 4);
+    d += 4;
+    lo >>= 32;
+  }
+  if (n & 2) {
+    const uint16_t h = (uint16_t)lo;
+    __builtin_memcpy(d, &h, 2);
+    d += 2;
+    lo >>= 16;
+  }
+  if (n & 1) *d = (uint8_t)lo;
+}
+__device__ __forceinline__ uint4 read16(const uint8_t* p) {
+  uint4 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+// copy len bytes (dst - src >= len, or >= 16) inside the window, no wrap
+__device__ __forceinline__ void copy_nowrap(uint8_t* ring, uint32_t dst, uint32_t src, uint32_t len) {
+  uint8_t* d = ring + (dst & kRingMask);
+  const uint8_t* q = ring + (src & kRingMask);
+  for (uint32_t k = 0; k < len; k += 16) write_upto16(d + k, read16(q + k), min(16u, len - k));
+}
+
 // Rare paths that read literal bytes straight from HBM (literal groups larger
 // than the staging ring, literal runs longer than the window).  They are kept
 // out of line so that their loads never merge with the registers of the LDS
@@ -662,61 +702,98 @@ __device__ void resolve_block(const LzArgs& a) {
     }
     uint32_t rounds = 0;
     bool split = false;
-    uint32_t lo = 0;
-    while (lo < m_cnt) {
-      uint32_t base = readlane(pos, lo);
-      {
-        // a literal run too long for the window is streamed through it first
-        uint32_t Llo = readlane(L, lo), Mlo = readlane(M, lo), slo = readlane(lsrc, lo);
-        while (Llo + Mlo > kSpanCap) {
-          const uint32_t P = kSpanCap / 2;
-          stream_lits_hbm(lits + slo, base, P, lane);
-          flush_window(a.out, flushed, base + P, false, lane, a.raw_len);
-          base += P;
-          slo += P;
-          Llo -= P;
-          split = true;
-        }
-        if (lane == lo) {
-          L = Llo;
-          lsrc = slo;
-          pos = base;
-        }
-      }
-      const uint64_t fit = __ballot(valid && lane >= lo && end - base <= kSpanCap);
-      const uint32_t hi = lo + (uint32_t)__popcll(fit);
-      if (hi < m_cnt) split = true;
-      const bool active = lane >= lo && lane < hi;
-      // A4: literal strings into the window
-      if (active && L) {
-        if (lits_staged) {
-          for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
-        } else {
-          copy_lits_hbm(lits + lsrc, pos, L);
-        }
+    // fast path: no copy of the group wraps around the window or the literal
+    // ring, none overlaps its own output, and the group fits the window
+    const uint32_t g_end = readlane(end, m_cnt - 1);
+    const uint32_t src0 = pos + L - D;
+    const bool lane_ok =
+        !valid || ((pos & kRingMask) + L + M <= kRing &&
+                   (M == 0 || (D >= M && (src0 & kRingMask) + ((M + 15) & ~15u) <= kRing)) &&
+                   (L == 0 || (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing));
+    const bool fast = lits_staged && g_end - readlane(pos, 0) <= kSpanCap && !__ballot(!lane_ok);
+    if (fast) {
+      if (valid && L) {
+        uint8_t* d = ring + (pos & kRingMask);
+        const uint8_t* q = lit_ring() + (lsrc & (kLitRing - 1));
+        for (uint32_t k = 0; k < L; k += 16) write_upto16(d + k, read16(q + k), min(16u, L - k));
       }
       const uint32_t dst = pos + L;
-      bool pending = active && M > 0;
+      bool pending = valid && M > 0;
       if (a.single_pass) {
         // A6: no back-reference of the group depends on another (DE)
-        if (__ballot(pending)) rounds += 1;
-        if (pending) copy_match(ring, dst, M, D);
+        if (__ballot(pending)) rounds = 1;
+        if (pending) copy_nowrap(ring, dst, src0, M);
       } else {
         // A5: Multi-Round Resolution
-        const uint32_t need_end = dst - D + min(M, D);
+        const uint32_t need_end = src0 + M;  // no overlap: the source is [src0, src0 + M)
         for (;;) {
           const uint64_t votes = __ballot(pending);
           if (votes == 0) break;
           const uint32_t hwm = readlane(dst, (uint32_t)__builtin_ctzll(votes));
-          if (pending && need_end <= hwm) {
-            copy_match(ring, dst, M, D);
-            pending = false;
-          }
+          const bool can = pending && need_end <= hwm;
+          if (can) copy_nowrap(ring, dst, src0, M);
+          pending = pending && !can;
           rounds++;
         }
       }
-      flush_window(a.out, flushed, readlane(end, hi - 1), false, lane, a.raw_len);
-      lo = hi;
+      flush_window(a.out, flushed, g_end, false, lane, a.raw_len);
+    } else {
+      uint32_t lo = 0;
+      while (lo < m_cnt) {
+        uint32_t base = readlane(pos, lo);
+        {
+          // a literal run too long for the window is streamed through it first
+          uint32_t Llo = readlane(L, lo), Mlo = readlane(M, lo), slo = readlane(lsrc, lo);
+          while (Llo + Mlo > kSpanCap) {
+            const uint32_t P = kSpanCap / 2;
+            stream_lits_hbm(lits + slo, base, P, lane);
+            flush_window(a.out, flushed, base + P, false, lane, a.raw_len);
+            base += P;
+            slo += P;
+            Llo -= P;
+            split = true;
+          }
+          if (lane == lo) {
+            L = Llo;
+            lsrc = slo;
+            pos = base;
+          }
+        }
+        const uint64_t fit = __ballot(valid && lane >= lo && end - base <= kSpanCap);
+        const uint32_t hi = lo + (uint32_t)__popcll(fit);
+        if (hi < m_cnt) split = true;
+        const bool active = lane >= lo && lane < hi;
+        // A4: literal strings into the window
+        if (active && L) {
+          if (lits_staged) {
+            for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
+          } else {
+            copy_lits_hbm(lits + lsrc, pos, L);
+          }
+        }
+        const uint32_t dst = pos + L;
+        bool pending = active && M > 0;
+        if (a.single_pass) {
+          // A6: no back-reference of the group depends on another (DE)
+          if (__ballot(pending)) rounds += 1;
+          if (pending) copy_match(ring, dst, M, D);
+        } else {
+          // A5: Multi-Round Resolution
+          const uint32_t need_end = dst - D + min(M, D);
+          for (;;) {
+            const uint64_t votes = __ballot(pending);
+            if (votes == 0) break;
+            const uint32_t hwm = readlane(dst, (uint32_t)__builtin_ctzll(votes));
+            if (pending && need_end <= hwm) {
+              copy_match(ring, dst, M, D);
+              pending = false;
+            }
+            rounds++;
+          }
+        }
+        flush_window(a.out, flushed, readlane(end, hi - 1), false, lane, a.raw_len);
+        lo = hi;
+      }
     }
     if (a.rounds && lane == 0) a.rounds[g] = (uint8_t)(min(rounds, 127u) | (split ? 0x80u : 0u));
     carry_lit += tot_lit;
@@ -855,7 +932,7 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
       sb.raw_off = raw_off;
       sb.seq_out = ws_seq + seq_off;
       sb.lit_out = ws_lit + lit_off;
-      const int e = decode_subblock<kDec>(sb, t, lut_ll, lut_d, lmax, window, max_match);
+      const int e = decode_subblock<kDec>(sb, t, lmax, window, max_match);
       lds_release(&sh.rd[t], kDone);
       if (e != kOK) set_err(e);
     }
