@@ -98,3 +98,33 @@ def decode_batch(ctx, blocks: list[bytes], flags: int = 0, waves: int = 1, persi
     r = rounds.cpu().numpy()
     rr = [r[goff[k]:goff[k + 1]].copy() for k in range(len(blocks))] if stats else None
     return status.cpu().numpy()[:len(blocks)], res, rr
+
+
+def decode_stream_batched(ctx, stream: bytes, flags: int = 0, waves: int = 1, persistent: bool = False):
+    """Decode a whole stream with one batch over its blocks, the launch shape the
+    benchmark times (one job per block, outputs contiguous).  Returns
+    (status array, output bytes); checks the guard bands."""
+    import struct
+
+    import paper_1606_00519_amd as gmp
+    torch = _torch()
+    nb, bs, total = gmp.stream_info(stream)
+    offs = struct.unpack_from(f"<{nb + 1}Q", stream, 32)
+    print(f"[gpu] decode_stream_batched blocks={nb} raw={total} flags={flags:#x} waves={waves} "
+          f"persistent={persistent}", flush=True)
+    d_in = to_device(stream)
+    buf = torch.full((total + 2 * GUARD,), CANARY, dtype=torch.uint8, device="cuda")
+    status = torch.full((max(nb, 1),), 12345, dtype=torch.int32, device="cuda")
+    jobs = []
+    for b in range(nb):
+        blk = stream[offs[b]:offs[b + 1]]
+        info = gmp.block_info(blk)
+        jobs.append(gmp.Job(d_in.data_ptr() + offs[b], len(blk), buf.data_ptr() + GUARD + b * bs, info["raw_len"],
+                            info["n_seq"], info["n_lit"], None))
+    batch = ctx.batch_create(jobs, status)
+    batch.run(flags, waves=waves, persistent=persistent)
+    torch.cuda.synchronize()
+    batch.close()
+    o = buf.cpu().numpy()
+    assert np.all(o[:GUARD] == CANARY) and np.all(o[GUARD + total:] == CANARY), "write outside the output"
+    return status.cpu().numpy()[:nb], o[GUARD:GUARD + total]
