@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -97,7 +99,7 @@ def oracle_leg(size: int, threads: int, cpu_seconds: float):
 
 
 # ----------------------------------------------------------------------------- GPU leg
-def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
+def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int, waves: int):
     import numpy as np
     import torch
 
@@ -137,7 +139,7 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
             r = runs[mode]
             if evs is not None:
                 evs[mode][0].record(stream)
-            r["batch"].run(r["flags"], waves=1, persistent=False)
+            r["batch"].run(r["flags"], waves=waves, persistent=False)
             if evs is not None:
                 evs[mode][1].record(stream)
 
@@ -160,7 +162,7 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
         if not np.array_equal(r["out"].cpu().numpy(), ref):
             raise RuntimeError(f"{mode}: GPU output differs from the original data")
         # untimed extra run: device wall-clock stamps per block (100 MHz ticks)
-        r["tbatch"].run(r["flags"] | gmp.FLAG_STATS, waves=1, persistent=False)
+        r["tbatch"].run(r["flags"] | gmp.FLAG_STATS, waves=waves, persistent=False)
         torch.cuda.synchronize()
         t = r["times"].cpu().numpy().astype(np.int64)
         d = np.diff(t, axis=1) * 10 / 1e3  # microseconds: tables, sub-block decode, resolution
@@ -181,6 +183,204 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int):
     return wall, kernel_ms, {m: runs[m]["comp"] for m in runs}, runs["mrr"]["blocks"], phases
 
 
+# ----------------------------------------------------------------------------- batched leg
+def _compress_blocks(raws, subs, des, threads):
+    """One oracle-compressed block per item (the item is the whole block)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    def one(k):
+        p = oracle.CompressParams(block_size=max(len(raws[k]), 1), window=32768, max_match=258, lmax=12,
+                                  sub_target_raw=subs[k], de=des[k], group=64)
+        return oracle.compress_block(raws[k], p)
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(len(raws))))
+
+
+class _DeviceBatch:
+    def __init__(self, ctx, blocks, raw_sizes):
+        import torch
+
+        import paper_1606_00519_amd as gmp
+        offs, pos = [], 0
+        for b in blocks:
+            offs.append(pos)
+            pos += (len(b) + 255) & ~255
+        host = bytearray(max(pos, 16))
+        for o, b in zip(offs, blocks):
+            host[o:o + len(b)] = b
+        self.d_in = torch.frombuffer(host, dtype=torch.uint8).cuda()
+        self.o_offs = np.concatenate([[0], np.cumsum(raw_sizes)]).astype(np.int64)
+        self.out = torch.empty(int(self.o_offs[-1]), dtype=torch.uint8, device="cuda")
+        self.status = torch.full((len(blocks),), 99, dtype=torch.int32, device="cuda")
+        jobs = []
+        for k, b in enumerate(blocks):
+            i = gmp.block_info(b)
+            jobs.append(gmp.Job(self.d_in.data_ptr() + offs[k], len(b), self.out.data_ptr() + int(self.o_offs[k]),
+                                i["raw_len"], i["n_seq"], i["n_lit"], None))
+        self.batch = ctx.batch_create(jobs, self.status)
+        self.comp = sum(len(b) for b in blocks)
+
+
+def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads: int):
+    """Thousands of independent blocks of uneven sizes (text and CSV, ordinary
+    and DE) in one graph-captured persistent launch: sub-block size chosen on
+    a sample by recompressing it, launch shape by the library's autotuner;
+    beside it the plain launch (one workgroup per block, one wavefront, no
+    graph) of the same blocks."""
+    import torch
+
+    import paper_1606_00519_amd as gmp
+    import synth
+    t0 = time.time()
+    csv = synth.csv_rows(1 << 30, threads=threads)
+    txt = np.frombuffer(text, np.uint8)
+    items = synth.batch_mix(n_items, text_corpus=len(txt), csv_corpus=len(csv))
+    raws = [(txt if it["kind"] == "text" else csv)[it["off"]:it["off"] + it["size"]].tobytes() for it in items]
+    des = [it["de"] for it in items]
+    del csv
+    total = sum(len(r) for r in raws)
+    log(f"batched: {len(raws)} items, {total / 2**30:.2f} GiB raw, generated in {time.time() - t0:.1f}s")
+    # sub-block size: recompress a sample at each candidate, autotune each
+    n_s = min(384, len(raws))
+    sub_res = {}
+    for sub in (4096, 8192, 16384, 32768):
+        blocks = _compress_blocks(raws[:n_s], [sub] * n_s, des[:n_s], threads)
+        db = _DeviceBatch(ctx, blocks, [len(r) for r in raws[:n_s]])
+        tun, ms = db.batch.autotune(gmp.MODE_AUTO, reps=3)
+        sub_res[sub] = (ms, tun)
+        db.batch.close()
+        del db
+        log(f"batched: sample sub-block {sub >> 10} KiB -> {ms:.3f} ms ({tun})")
+    best_sub = min(sub_res, key=lambda k: sub_res[k][0])
+    t0 = time.time()
+    blocks = _compress_blocks(raws, [best_sub] * len(raws), des, threads)
+    log(f"batched: compressed all items at {best_sub >> 10} KiB sub-blocks in {time.time() - t0:.1f}s")
+    db = _DeviceBatch(ctx, blocks, [len(r) for r in raws])
+    del blocks
+    tun, tms = db.batch.autotune(gmp.MODE_AUTO, reps=3)
+    db.batch.graph_create(gmp.MODE_AUTO, waves=tun["waves"], persistent=tun["persistent"],
+                          workgroups=tun["workgroups"])
+    stream = torch.cuda.current_stream()
+
+    def timed(run):
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in evs:
+            a.record(stream)
+            run()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    def check(what):
+        st = db.status.cpu().numpy()
+        if not np.all(st == 0):
+            raise RuntimeError(f"batched ({what}): device status {st[st != 0][:8]}")
+        got = db.out.cpu().numpy()
+        for k, r in enumerate(raws):
+            if got[db.o_offs[k]:db.o_offs[k + 1]].tobytes() != r:
+                raise RuntimeError(f"batched ({what}): item {k} differs from its source bytes")
+
+    graph_ms = timed(lambda: db.batch.graph_launch())
+    check("graph")
+    db.out.zero_()
+    plain_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=1, persistent=False))
+    check("plain")
+    res = {"items": len(raws), "raw_bytes": total, "compressed_bytes": db.comp,
+           "sub_block_kib": best_sub >> 10, "tuning": tun,
+           "sample_ms_by_sub_block_kib": {k >> 10: round(v[0], 3) for k, v in sub_res.items()},
+           "graph_ms": round(graph_ms, 3), "GBps": round(total / graph_ms / 1e6, 3),
+           "plain_ms": round(plain_ms, 3), "plain_GBps": round(total / plain_ms / 1e6, 3)}
+    db.batch.close()
+    log(f"batched: graph {graph_ms:.2f} ms ({res['GBps']} GB/s), plain {plain_ms:.2f} ms ({res['plain_GBps']} GB/s)")
+    return res
+
+
+# ----------------------------------------------------------------------------- serving leg
+def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threads: int, budget: int = 64 << 30):
+    """Poisson arrivals of requests (log-uniform 64 KiB-64 MiB, text or CSV,
+    ordinary or DE) at offered loads of 10-90 % of the batched peak, admitted
+    by the library's request loop within an HBM budget; the requests' buffers
+    are resident on the device before the clock starts.  Reports achieved
+    GB/s, p50/p99 latency (completion - arrival) and admission wait."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import oracle
+    import paper_1606_00519_amd as gmp
+    import synth
+    t0 = time.time()
+    csv = synth.csv_rows(1 << 30, threads=threads)
+    txt = np.frombuffer(text, np.uint8)
+    spec = synth.request_mix(n_pool, text_corpus=len(txt), csv_corpus=len(csv))
+    raws = [(txt if r["kind"] == "text" else csv)[r["off"]:r["off"] + r["size"]].tobytes() for r in spec]
+    del csv
+
+    def comp(k):
+        r = spec[k]
+        p = (oracle.CompressParams(block_size=1 << 20, sub_target_raw=16384, de=r["de"]) if r["kind"] == "text"
+             else oracle.CompressParams(block_size=2 << 20, sub_target_raw=32768, de=r["de"]))
+        return oracle.compress(raws[k], p, threads=1)
+
+    with ThreadPoolExecutor(threads) as ex:
+        streams = list(ex.map(comp, range(n_pool)))
+    log(f"serve: pool of {n_pool} requests ({sum(map(len, raws)) / 2**30:.2f} GiB raw) ready in "
+        f"{time.time() - t0:.1f}s")
+    pool = []
+    for raw, s in zip(raws, streams):
+        nb = gmp.stream_info(s)[0]
+        pool.append({"d_in": torch.frombuffer(bytearray(s), dtype=torch.uint8).cuda(), "h": s,
+                     "out": torch.empty(len(raw), dtype=torch.uint8, device="cuda"),
+                     "status": torch.full((nb,), 99, dtype=torch.int32, device="cuda"), "raw": raw})
+    torch.cuda.synchronize()
+    mean_u = float(np.mean([len(r) for r in raws]))
+    srv = gmp.Server(ctx, budget_bytes=budget, slots=16)
+    rng = np.random.default_rng(synth.SERVE_SEED + 100)
+    levels = []
+    for rho in (0.1, 0.3, 0.5, 0.7, 0.9):
+        lam = rho * peak_gbps * 1e9 / mean_u
+        arr = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        which = rng.integers(0, n_pool, n_req)
+        done = []
+        t_start = time.perf_counter()
+        for i in range(n_req):
+            while time.perf_counter() - t_start < arr[i]:
+                pass
+            e = pool[which[i]]
+            srv.submit(e["d_in"], e["h"], e["out"], e["status"], gmp.MODE_AUTO, tag=i)
+            if i % 64 == 0:
+                done += srv.poll(4096)
+        srv.drain(600000)
+        done += srv.poll(1 << 16)
+        if len(done) != n_req or any(c["status"] != 0 for c in done):
+            raise RuntimeError(f"serve: {len(done)} of {n_req} requests completed, or a request failed")
+        lat = np.array([(c["t_done_ns"] - c["t_submit_ns"]) / 1e6 for c in done])
+        wait = np.array([(c["t_admit_ns"] - c["t_submit_ns"]) / 1e6 for c in done])
+        span = (max(c["t_done_ns"] for c in done) - min(c["t_submit_ns"] for c in done)) / 1e9
+        byt = sum(c["bytes"] for c in done)
+        lv = {"rho": rho, "offered_GBps": round(lam * mean_u / 1e9, 3), "achieved_GBps": round(byt / span / 1e9, 3),
+              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+              "admit_wait_p50_ms": round(float(np.percentile(wait, 50)), 3),
+              "admit_wait_p99_ms": round(float(np.percentile(wait, 99)), 3), "requests": n_req}
+        levels.append(lv)
+        log(f"serve: rho {rho}: {lv}")
+    info = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    for e in pool:
+        if not np.all(e["status"].cpu().numpy() == 0) or e["out"].cpu().numpy().tobytes() != e["raw"]:
+            raise RuntimeError("serve: a pooled request's output differs from its source bytes")
+    return {"pool_requests": n_pool, "mean_request_bytes": int(mean_u), "budget_bytes": budget, "slots": 16,
+            "peak_in_flight_bytes": info["peak_in_flight_bytes"], "peak_concurrent": info["peak_slots"],
+            "reference_peak_GBps": round(peak_gbps, 3), "levels": levels}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +389,11 @@ def main() -> int:
     ap.add_argument("--size-mib", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--waves", type=int, default=4, choices=(1, 2, 4),
+                    help="decoder (phase A) and resolver (phase B) wavefronts per block")
+    ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serving: requests per load level (0 = skip)")
+    ap.add_argument("--serve-pool", type=int, default=192, help="serving: distinct device-resident requests")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device-to-device copy of the output size (a reference kernel "
                          "for scaling hardware traffic counters)")
@@ -206,7 +411,17 @@ def main() -> int:
         dst.copy_(src)  # reads and writes exactly `size` bytes
         torch.cuda.synchronize()
         del src, dst
-    wall, kernel_ms, comp, n_blocks, phases = gpu_leg(data, streams, args.steps, args.warmup)
+    wall, kernel_ms, comp, n_blocks, phases = gpu_leg(data, streams, args.steps, args.warmup, args.waves)
+    batched = serving = None
+    if args.batch_items > 0 or args.serve_requests > 0:
+        import paper_1606_00519_amd as gmp
+        ctx = gmp.Context(0)
+        if args.batch_items > 0:
+            batched = batched_leg(ctx, data, args.batch_items, min(args.steps, 5), 1, args.threads)
+        if args.serve_requests > 0:
+            peak = batched["GBps"] if batched else size / (kernel_ms["mrr"] / 1e3) / 1e9
+            serving = serve_leg(ctx, data, peak, args.serve_pool, args.serve_requests, args.threads)
+        ctx.close()
     raw_step = 2 * size
     ms_per_step = wall / args.steps * 1e3
     value = raw_step / (wall / args.steps) / 1e9
@@ -232,13 +447,17 @@ def main() -> int:
         "config": {"workload": f"zipf-text {args.size_mib} MiB, 1 MiB blocks x 64 sub-blocks of 16 KiB, "
                                f"window 32 KiB, matches 3-258, lmax 12; one MRR stream and one DE stream of "
                                f"the same data per step",
-                   "raw_bytes_per_step": raw_step, "blocks_per_stream": n_blocks, "launch": "1 wave/block"},
+                   "raw_bytes_per_step": raw_step, "blocks_per_stream": n_blocks, "launch": f"one workgroup per block: {args.waves} decoder/resolver wave(s) + fetcher + flusher"},
         "modes": modes,
         "roofline": {"bound": "hbm", "kernel": f"inflate_kernel ({dom})", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5),
                      "traffic": traffic},
         "cpu_baseline": baseline,
     }
+    if batched:
+        line["batched"] = batched
+    if serving:
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
     return 0
 

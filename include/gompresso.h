@@ -66,6 +66,9 @@ typedef int32_t gmp_status;
 #define GMP_ENOMEM -9   /* device or host allocation failed */
 #define GMP_EBUSY -10   /* no capacity (serving back-pressure) */
 #define GMP_ENOSYS -11  /* valid format feature this decoder does not implement (lmax > 13) */
+#define GMP_ESTALL -12  /* a device-side wait exceeded its time bound (about 1 s); the block's
+                           output is incomplete.  An internal error: the kernel bounds every
+                           wait so that a fault in its hand-over logic ends instead of hanging */
 
 /* flags */
 #define GMP_MODE_AUTO 0u  /* single pass if the block says DE and its group is a multiple of 64, else MRR */
@@ -104,10 +107,11 @@ typedef struct {
 /* Tuning of the batched kernel (section "Dependency on Data Block Size":
  * sub-block count sets the Huffman parallelism per block). */
 typedef struct {
-  uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2 or 4 (Huffman lanes = 64 x waves); each
-                               workgroup adds one fetcher wavefront that streams HBM into LDS */
+  uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2 or 4 (Huffman lanes = 64 x waves); they
+                               also resolve back-references, groups round-robin.  Each workgroup adds a
+                               fetcher wavefront (HBM -> LDS) and a flusher wavefront (output -> HBM) */
   uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
-  uint32_t workgroups;      /* persistent grid size (0 = 2 per compute unit) */
+  uint32_t workgroups;      /* persistent grid size (0 = one per compute unit) */
   uint32_t reserved;
 } gmp_tuning;
 
@@ -144,11 +148,93 @@ gmp_status gmp_decompress_stream(gmp_ctx* ctx, const uint8_t* d_stream, const vo
 
 /* ---- batch of independent blocks (one launch over a device job table) ------------ */
 /* Upload a job table once; run it any number of times.  d_status: n_jobs int32 on
- * the device.  The batch owns its device job table and workspace. */
+ * the device; job i's status goes to d_status[i].  The batch owns its device job
+ * table and workspace.  Jobs are dispatched largest first (by out_len), which
+ * evens out the finish times of uneven blocks. */
 gmp_status gmp_batch_create(gmp_ctx* ctx, const gmp_job* h_jobs, uint32_t n_jobs, int32_t* d_status,
                             gmp_batch** out);
 gmp_status gmp_batch_run(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, const gmp_tuning* tuning, void* stream);
 void gmp_batch_destroy(gmp_batch* batch);
+
+/* ---- graph-captured batch (one launch decodes the whole batch) ------------------- */
+/* Capture the batch's launch with these flags and tuning into a HIP graph owned by
+ * the batch (blocks are independent, section "Gompresso Overview", so a single
+ * launch serves any number of them).  The graph holds a small kernel that resets
+ * the persistent queue (no memset node) and the decode kernel.  A new capture
+ * replaces the previous graph.  EINVAL on bad flags or tuning; EDEVICE if capture
+ * or instantiation fails. */
+gmp_status gmp_batch_graph_create(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, const gmp_tuning* tuning);
+/* Replay the captured graph on `stream`; EINVAL if none was captured. */
+gmp_status gmp_batch_graph_launch(gmp_ctx* ctx, gmp_batch* batch, void* stream);
+
+/* ---- autotuner ---------------------------------------------------------------- */
+/* Choose launch parameters for a batch by timing candidates on the device
+ * (section "Dependency on Data Block Size": parallelism per block against
+ * per-block overheads): wavefronts per block in {1, 2, 4} x {one workgroup per
+ * job, persistent with one or two workgroups per compute unit}.  Each candidate
+ * runs once untimed, then `reps` (1..64) timed runs on `stream`; the least
+ * median wins.  The batch's outputs are overwritten (with the same bytes, for
+ * valid input).  *best receives the winner, *best_ms (may be NULL) its median
+ * time.  Synchronous. */
+gmp_status gmp_autotune(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, uint32_t reps, gmp_tuning* best,
+                        float* best_ms, void* stream);
+
+/* ---- request loop (continuous batching on one GPU) ------------------------------ */
+/* A server admits decompression requests of mixed sizes as they arrive and runs
+ * them concurrently: a scheduler thread admits requests first come first served
+ * while the bytes of everything in flight (compressed + decompressed + token
+ * workspace) stay within `budget_bytes` and one of `n_slots` execution slots
+ * (a HIP stream each, default priority) is free, launches each admitted
+ * request's blocks on its slot (one workgroup per block; blocks are
+ * independent, section "Gompresso Overview"), and on completion frees budget,
+ * workspace and slot and admits the next ones.  Work of requests admitted at
+ * different times overlaps on the device.  Compressed input, output and status
+ * words belong to the caller and stay resident on the device; the server owns a
+ * token-workspace arena of `workspace_bytes` (0 = budget / 2), handed out
+ * first-fit.  A request whose bytes exceed the budget can never be admitted
+ * and is refused by gmp_server_submit with GMP_EBUSY. */
+typedef struct gmp_server gmp_server;
+
+typedef struct {
+  const uint8_t* d_stream; /* device: a whole stream (gmp_decompress_stream's input) */
+  const void* h_stream;    /* host copy of the stream's header, block table and block headers/indexes */
+  uint64_t len;            /* stream bytes (at d_stream and h_stream) */
+  uint8_t* d_out;          /* device output, out_len = the stream's raw_total */
+  uint64_t out_len;
+  int32_t* d_status;       /* device: one int32 per block */
+  uint32_t flags;          /* GMP_MODE_* */
+  uint32_t reserved;
+  uint64_t tag;            /* caller's identifier, returned in the completion */
+} gmp_request;
+
+typedef struct {
+  uint64_t tag;
+  int32_t status;          /* GMP_OK once the launch completed (per-block results are in d_status);
+                              else the host-side or HIP error that ended the request */
+  uint32_t reserved;
+  uint64_t bytes;          /* decompressed bytes of the request */
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* host steady clock */
+} gmp_completion;
+
+typedef struct {
+  uint64_t submitted, finished, pending;
+  uint64_t in_flight_bytes, peak_in_flight_bytes, budget;
+  uint32_t peak_slots, reserved;
+} gmp_server_info;
+
+gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uint64_t workspace_bytes, uint32_t n_slots,
+                             const gmp_tuning* tuning, gmp_server** out);
+/* Queue a request (thread-safe).  The header and block table are checked here:
+ * EFORMAT / ESIZE / EINVAL as for gmp_decompress_stream; EBUSY if the request
+ * alone exceeds the budget. */
+gmp_status gmp_server_submit(gmp_server* srv, const gmp_request* req);
+/* Move up to `max` completions (in completion order) to `out`; returns how many. */
+uint32_t gmp_server_poll(gmp_server* srv, gmp_completion* out, uint32_t max);
+/* Wait until every submitted request has completed (EBUSY on timeout). */
+gmp_status gmp_server_drain(gmp_server* srv, uint32_t timeout_ms);
+gmp_status gmp_server_stats(gmp_server* srv, gmp_server_info* out);
+/* Drops requests not yet admitted, waits for the admitted ones, frees everything. */
+void gmp_server_destroy(gmp_server* srv);
 
 #ifdef __cplusplus
 }

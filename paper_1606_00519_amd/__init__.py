@@ -22,14 +22,16 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgompresso_hip.so")
 
-OK, EINVAL, EFORMAT, ECODE, EDIST, ELEN, ESIZE, ESUB, EDEVICE, ENOMEM, EBUSY, ENOSYS = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11)
+OK, EINVAL, EFORMAT, ECODE, EDIST, ELEN, ESIZE, ESUB, EDEVICE, ENOMEM, EBUSY, ENOSYS, ESTALL = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12)
 MODE_AUTO, MODE_MRR, MODE_DE = 0, 1, 2
 FLAG_STATS = 0x100
 
 EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_block_info_parse", "gmp_stream_info",
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",
-           "gmp_batch_destroy")
+           "gmp_batch_destroy", "gmp_batch_graph_create", "gmp_batch_graph_launch", "gmp_autotune",
+           "gmp_server_create", "gmp_server_submit", "gmp_server_poll", "gmp_server_drain", "gmp_server_stats",
+           "gmp_server_destroy")
 
 
 class GmpError(RuntimeError):
@@ -46,6 +48,23 @@ class BlockInfo(C.Structure):
 class Job(C.Structure):
     _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("d_out", C.c_void_p), ("out_len", C.c_uint64),
                 ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("d_stream", C.c_void_p), ("h_stream", C.c_void_p), ("len", C.c_uint64), ("d_out", C.c_void_p),
+                ("out_len", C.c_uint64), ("d_status", C.c_void_p), ("flags", C.c_uint32), ("reserved", C.c_uint32),
+                ("tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_uint32), ("bytes", C.c_uint64),
+                ("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("finished", C.c_uint64), ("pending", C.c_uint64),
+                ("in_flight_bytes", C.c_uint64), ("peak_in_flight_bytes", C.c_uint64), ("budget", C.c_uint64),
+                ("peak_slots", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Tuning(C.Structure):
@@ -71,8 +90,21 @@ def _load():
     L.gmp_batch_run.argtypes = [vp, vp, u32, C.POINTER(Tuning), vp]
     L.gmp_batch_destroy.argtypes = [vp]
     L.gmp_batch_destroy.restype = None
+    L.gmp_batch_graph_create.argtypes = [vp, vp, u32, C.POINTER(Tuning)]
+    L.gmp_batch_graph_launch.argtypes = [vp, vp, vp]
+    L.gmp_autotune.argtypes = [vp, vp, u32, u32, C.POINTER(Tuning), C.POINTER(C.c_float), vp]
+    L.gmp_server_create.argtypes = [vp, C.c_uint64, C.c_uint64, u32, C.POINTER(Tuning), C.POINTER(vp)]
+    L.gmp_server_submit.argtypes = [vp, C.POINTER(Request)]
+    L.gmp_server_poll.argtypes = [vp, C.POINTER(Completion), u32]
+    L.gmp_server_poll.restype = u32
+    L.gmp_server_drain.argtypes = [vp, u32]
+    L.gmp_server_stats.argtypes = [vp, C.POINTER(ServerInfo)]
+    L.gmp_server_destroy.argtypes = [vp]
+    L.gmp_server_destroy.restype = None
     for fn in ("gmp_ctx_create", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
-               "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run"):
+               "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run", "gmp_batch_graph_create",
+               "gmp_batch_graph_launch", "gmp_autotune", "gmp_server_create", "gmp_server_submit",
+               "gmp_server_drain", "gmp_server_stats"):
         getattr(L, fn).restype = i32
     return L
 
@@ -110,7 +142,11 @@ def block_info(h_block) -> dict:
 
 
 def stream_info(h_stream) -> tuple[int, int, int]:
-    p, n, keep = _host(h_stream[:4096] if not isinstance(h_stream, np.ndarray) else h_stream)
+    if not isinstance(h_stream, np.ndarray):
+        head = bytes(h_stream[:32])
+        nb = int.from_bytes(head[12:16], "little") if len(head) >= 16 else 0
+        h_stream = h_stream[:32 + 8 * (nb + 1)]  # header and block table only
+    p, n, keep = _host(h_stream)
     nb, bs, tot = C.c_uint32(), C.c_uint32(), C.c_uint64()
     st = lib.gmp_stream_info(p, n, C.byref(nb), C.byref(bs), C.byref(tot))
     if st:
@@ -139,9 +175,91 @@ class Batch:
         if st:
             raise GmpError(st, "gmp_batch_run")
 
+    def graph_create(self, flags: int = MODE_AUTO, waves: int = 1, persistent: bool = True,
+                     workgroups: int = 0) -> None:
+        """Capture this batch's launch as a HIP graph (gmp_batch_graph_create)."""
+        t = Tuning(waves, int(persistent), workgroups, 0)
+        st = lib.gmp_batch_graph_create(self.ctx.handle, self.handle, flags, C.byref(t))
+        if st:
+            raise GmpError(st, "gmp_batch_graph_create")
+
+    def graph_launch(self, stream=None) -> None:
+        st = lib.gmp_batch_graph_launch(self.ctx.handle, self.handle, _stream_handle(stream))
+        if st:
+            raise GmpError(st, "gmp_batch_graph_launch")
+
+    def autotune(self, flags: int = MODE_AUTO, reps: int = 3, stream=None) -> tuple[dict, float]:
+        """Time the launch candidates (gmp_autotune); returns (tuning, median ms)."""
+        t, ms = Tuning(), C.c_float()
+        st = lib.gmp_autotune(self.ctx.handle, self.handle, flags, reps, C.byref(t), C.byref(ms),
+                              _stream_handle(stream))
+        if st:
+            raise GmpError(st, "gmp_autotune")
+        return ({"waves": t.waves_per_block, "persistent": bool(t.persistent), "workgroups": t.workgroups},
+                float(ms.value))
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             lib.gmp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """gmp_server: continuous batching of decompression requests on one GPU.
+
+    submit() takes device-resident stream bytes (torch uint8 CUDA tensor), a host copy
+    of the stream (for its headers), an output tensor and a per-block int32 status
+    tensor; the caller keeps them alive until the request's completion is polled."""
+
+    def __init__(self, ctx: "Context", budget_bytes: int, workspace_bytes: int = 0, slots: int = 8,
+                 waves: int = 1):
+        self.ctx = ctx
+        t = Tuning(waves, 0, 0, 0)
+        h = C.c_void_p()
+        st = lib.gmp_server_create(ctx.handle, budget_bytes, workspace_bytes, slots, C.byref(t), C.byref(h))
+        if st:
+            raise GmpError(st, "gmp_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, d_stream, h_stream, out, status, flags: int = MODE_AUTO, tag: int = 0) -> None:
+        p, n, keep = _host(h_stream)
+        r = Request(d_stream.data_ptr(), p, n, out.data_ptr(), out.numel(), status.data_ptr(), flags, 0, tag)
+        st = lib.gmp_server_submit(self.handle, C.byref(r))
+        if st:
+            raise GmpError(st, "gmp_server_submit")
+        self._keep[tag] = keep
+
+    def poll(self, max_n: int = 256) -> list[dict]:
+        arr = (Completion * max_n)()
+        n = lib.gmp_server_poll(self.handle, arr, max_n)
+        out = []
+        for c in arr[:n]:
+            self._keep.pop(c.tag, None)
+            out.append({f: getattr(c, f) for f, _ in Completion._fields_ if f != "reserved"})
+        return out
+
+    def drain(self, timeout_ms: int = 60000) -> None:
+        st = lib.gmp_server_drain(self.handle, timeout_ms)
+        if st:
+            raise GmpError(st, "gmp_server_drain")
+
+    def stats(self) -> dict:
+        i = ServerInfo()
+        st = lib.gmp_server_stats(self.handle, C.byref(i))
+        if st:
+            raise GmpError(st, "gmp_server_stats")
+        return {f: getattr(i, f) for f, _ in ServerInfo._fields_ if f != "reserved"}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.gmp_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

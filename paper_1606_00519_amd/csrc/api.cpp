@@ -3,9 +3,11 @@
 // kernels of inflate.hip; this file only marshals arguments.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "../../include/gompresso.h"
@@ -61,6 +63,9 @@ struct gmp_batch {
   uint8_t* d_ws = nullptr;
   uint32_t* d_queue = nullptr;
   int num_cu = 0;
+  hipStream_t capture = nullptr;  // stream used for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 extern "C" const char* gmp_strerror(gmp_status s) {
@@ -77,6 +82,7 @@ extern "C" const char* gmp_strerror(gmp_status s) {
     case GMP_ENOMEM: return "out of memory";
     case GMP_EBUSY: return "no capacity";
     case GMP_ENOSYS: return "format feature not supported by this decoder";
+    case GMP_ESTALL: return "device-side wait exceeded its bound (internal error)";
     default: return "unknown status";
   }
 }
@@ -293,10 +299,17 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     gmp_batch_destroy(b);
     return GMP_ENOMEM;
   }
+  // largest blocks first: the queue (and the hardware's workgroup order) then
+  // hands the long jobs out early and the short ones fill the tail
+  std::vector<uint32_t> order(n_jobs);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t x, uint32_t y) { return h_jobs[x].out_len > h_jobs[y].out_len; });
   uint64_t ws_off = 0;
-  for (uint32_t i = 0; i < n_jobs; i++) {
+  for (uint32_t k = 0; k < n_jobs; k++) {
+    const uint32_t i = order[k];
     const gmp_job& j = h_jobs[i];
-    gmpk::DevJob& d = dj[i];
+    gmpk::DevJob& d = dj[k];
     d.comp = j.d_comp;
     d.comp_len = j.comp_len;
     d.out = j.d_out;
@@ -318,26 +331,137 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
   return GMP_OK;
 }
 
+namespace {
+
+struct Launch {
+  uint32_t waves = 1, persistent = 0, workgroups = 0;
+};
+
+gmp_status launch_params(const gmp_batch* b, const gmp_tuning* tuning, Launch* l) {
+  Launch x;
+  if (tuning) {
+    x.waves = tuning->waves_per_block;
+    x.persistent = tuning->persistent;
+    x.workgroups = tuning->workgroups;
+  }
+  if (x.waves != 1 && x.waves != 2 && x.waves != 4) return GMP_EINVAL;
+  if (x.persistent > 1) return GMP_EINVAL;
+  if (x.persistent && x.workgroups == 0) x.workgroups = (uint32_t)b->num_cu;
+  *l = x;
+  return GMP_OK;
+}
+
+gmp_status batch_launch(gmp_batch* b, uint32_t flags, const Launch& l, hipStream_t s) {
+  if (gmpk_launch(b->d_jobs, b->n, flags, l.waves, l.persistent, l.workgroups, b->d_queue, s) != 0)
+    return GMP_EDEVICE;
+  return GMP_OK;
+}
+
+void graph_release(gmp_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
 extern "C" gmp_status gmp_batch_run(gmp_ctx* c, gmp_batch* b, uint32_t flags, const gmp_tuning* tuning, void* stream) {
   if (!c || !b || !valid_flags(flags)) return GMP_EINVAL;
-  uint32_t waves = 1, persistent = 0, wgs = 0;
-  if (tuning) {
-    waves = tuning->waves_per_block;
-    persistent = tuning->persistent;
-    wgs = tuning->workgroups;
-  }
-  if (waves != 1 && waves != 2 && waves != 4) return GMP_EINVAL;
-  if (persistent && wgs == 0) wgs = 2u * (uint32_t)b->num_cu;
+  Launch l;
+  gmp_status st = launch_params(b, tuning, &l);
+  if (st != GMP_OK) return st;
   if (b->n == 0) return GMP_OK;
   HIP_OK(hipSetDevice(b->device));
-  if (gmpk_launch(b->d_jobs, b->n, flags, waves, persistent, wgs, b->d_queue, static_cast<hipStream_t>(stream)) != 0)
+  return batch_launch(b, flags, l, static_cast<hipStream_t>(stream));
+}
+
+extern "C" gmp_status gmp_batch_graph_create(gmp_ctx* c, gmp_batch* b, uint32_t flags, const gmp_tuning* tuning) {
+  if (!c || !b || !valid_flags(flags)) return GMP_EINVAL;
+  Launch l;
+  gmp_status st = launch_params(b, tuning, &l);
+  if (st != GMP_OK) return st;
+  HIP_OK(hipSetDevice(b->device));
+  graph_release(b);
+  if (!b->capture) HIP_OK(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+  st = b->n ? batch_launch(b, flags, l, b->capture) : GMP_OK;
+  hipGraph_t g = nullptr;
+  const hipError_t end = hipStreamEndCapture(b->capture, &g);
+  if (st != GMP_OK || end != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
     return GMP_EDEVICE;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    graph_release(b);
+    return GMP_EDEVICE;
+  }
+  return GMP_OK;
+}
+
+extern "C" gmp_status gmp_batch_graph_launch(gmp_ctx* c, gmp_batch* b, void* stream) {
+  if (!c || !b || !b->exec) return GMP_EINVAL;
+  HIP_OK(hipSetDevice(b->device));
+  HIP_OK(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return GMP_OK;
+}
+
+extern "C" gmp_status gmp_autotune(gmp_ctx* c, gmp_batch* b, uint32_t flags, uint32_t reps, gmp_tuning* best,
+                                   float* best_ms, void* stream) {
+  if (!c || !b || !best || !valid_flags(flags) || (flags & GMP_FLAG_STATS) || reps < 1 || reps > 64)
+    return GMP_EINVAL;
+  HIP_OK(hipSetDevice(b->device));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<Launch> cands;
+  for (uint32_t w : {1u, 2u, 4u}) {
+    cands.push_back({w, 0u, 0u});
+    cands.push_back({w, 1u, (uint32_t)b->num_cu});
+    cands.push_back({w, 1u, 2u * (uint32_t)b->num_cu});
+  }
+  std::vector<hipEvent_t> ev(reps + 1, nullptr);
+  gmp_status st = GMP_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = GMP_EDEVICE;
+  float best_t = -1.0f;
+  Launch win = cands[0];
+  for (size_t k = 0; st == GMP_OK && k < cands.size(); k++) {
+    if (b->n && (st = batch_launch(b, flags, cands[k], s)) != GMP_OK) break;  // untimed warm-up
+    if (hipEventRecord(ev[0], s) != hipSuccess) st = GMP_EDEVICE;
+    for (uint32_t r = 0; st == GMP_OK && r < reps; r++) {
+      if (b->n) st = batch_launch(b, flags, cands[k], s);
+      if (st == GMP_OK && hipEventRecord(ev[r + 1], s) != hipSuccess) st = GMP_EDEVICE;
+    }
+    if (st != GMP_OK || hipEventSynchronize(ev[reps]) != hipSuccess) {
+      st = st == GMP_OK ? GMP_EDEVICE : st;
+      break;
+    }
+    std::vector<float> t(reps);
+    for (uint32_t r = 0; r < reps; r++)
+      if (hipEventElapsedTime(&t[r], ev[r], ev[r + 1]) != hipSuccess) st = GMP_EDEVICE;
+    std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+    const float med = t[reps / 2];
+    if (best_t < 0 || med < best_t) {
+      best_t = med;
+      win = cands[k];
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st != GMP_OK) return st;
+  best->waves_per_block = win.waves;
+  best->persistent = win.persistent;
+  best->workgroups = win.workgroups;
+  best->reserved = 0;
+  if (best_ms) *best_ms = best_t;
   return GMP_OK;
 }
 
 extern "C" void gmp_batch_destroy(gmp_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
+  graph_release(b);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_queue) (void)hipFree(b->d_queue);

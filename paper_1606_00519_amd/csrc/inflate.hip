@@ -86,11 +86,12 @@ constexpr uint32_t kStageBytes = 32768;       // staging area: bit rings, then t
 constexpr uint32_t kRecRing = 2048;           // staged sequence records (8 bytes each)
 constexpr uint32_t kLitRing = 8192;           // staged literal bytes
 constexpr uint32_t kLitStagedMax = 4096;      // larger literal groups read HBM directly
+constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
 
 // status codes (same values as the public header)
 constexpr int kOK = 0, kEINVAL = -1, kEFORMAT = -2, kECODE = -3, kEDIST = -4, kELEN = -5, kESIZE = -6,
-              kESUB = -7, kENOSYS = -11;
+              kESUB = -7, kENOSYS = -11, kESTALL = -12;
 
 // Lookup-table entry: bits 0-4 bits consumed by the lookup (0 = invalid
 // entry), 5-8 further extra bits to read, 9-10 kind, 16-31 value (literal
@@ -155,14 +156,18 @@ constexpr int kMaxLanes = 64 * kMaxDecWaves;
 struct Misc {
   uint8_t lens[kNumLL + kNumD];
   uint32_t count[16], first[16];
-  uint32_t wave_sum[4][kMaxDecWaves + 1];
+  uint32_t wave_sum[4][kMaxDecWaves + 2];
   uint32_t sub_woff[kMaxLanes];  // first payload word of each lane's sub-block
   uint32_t sub_nw[kMaxLanes];    // its words, a multiple of 4 (0: nothing to fetch)
   uint32_t rd[kMaxLanes];        // decoder -> fetcher: words taken from the lane's bit ring
   uint32_t avail[kMaxLanes];     // fetcher -> decoder: words present in the lane's bit ring
-  uint32_t rec_avail, lit_avail;  // fetcher -> resolver: records / literal bytes staged
-  uint32_t rec_cons, lit_cons;    // resolver -> fetcher: records / literal bytes consumed
+  uint32_t rec_avail, lit_avail;  // fetcher -> resolvers: records / literal bytes staged
+  uint32_t g_out[kGRing], g_lit[kGRing];   // fetcher -> resolvers: offsets of staged groups
+  uint32_t next_group[kMaxDecWaves];       // resolver -> fetcher: first group it still reads
+  uint32_t done_upto;                      // resolvers: output below this is final
+  uint32_t flushed;                        // flusher: output below this is in HBM
   uint32_t next_job;
+  uint32_t abort;  // set when a wait exceeded its bound: every wavefront stops waiting
   int err;
 };
 
@@ -176,6 +181,29 @@ __device__ __forceinline__ uint2* rec_ring() { return reinterpret_cast<uint2*>(s
 __device__ __forceinline__ uint8_t* lit_ring() { return reinterpret_cast<uint8_t*>(s_stage) + 8 * kRecRing; }
 
 __device__ __forceinline__ void set_err(int e) { atomicCAS(&s_misc.err, 0, e); }
+
+// Every wait on another wavefront is bounded: a wait that lasts longer than
+// about a second (the constant 100 MHz clock), or that sees another
+// wavefront give up, ends, and the block reports kESTALL.  A correct
+// hand-over never comes near the bound; the bound only guarantees that a
+// fault in the hand-over logic ends the kernel instead of hanging it.
+constexpr uint64_t kSpinTicks = 100000000ull;
+struct Spin {
+  uint64_t t0 = 0;
+  // one pause of a wait loop; false when the wait must end
+  __device__ __forceinline__ bool pause() {
+    if (__hip_atomic_load(&s_misc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+    const uint64_t now = (uint64_t)wall_clock64();
+    if (t0 == 0) {
+      t0 = now;
+    } else if (now - t0 > kSpinTicks) {
+      __hip_atomic_store(&s_misc.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
+  }
+};
 
 // Asynchronous copy of 1 KiB from HBM into LDS: lane l moves the 16 bytes at
 // its src to lds + 16*l (lds is the same for all lanes).
@@ -318,6 +346,7 @@ __device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
     woff[v] = s_misc.sub_woff[f + 64 * v];
     fetched[v] = 0;
   }
+  Spin sp;
   for (;;) {
     bool left = false, issued = false;
     uint32_t limit[kDec];
@@ -348,8 +377,9 @@ __device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
         fetched[v] = limit[v];
         lds_release(&s_misc.avail[f + 64 * v], fetched[v]);
       }
-    } else {
-      __builtin_amdgcn_s_sleep(2);
+      sp = Spin();
+    } else if (!sp.pause()) {
+      return;
     }
   }
 }
@@ -385,10 +415,14 @@ __device__ int decode_subblock(const SubBlock& sb, uint32_t L, uint32_t lmax, ui
   // word k of the lane's stream (zero past its end); waits for the fetcher when needed
   auto ring_word = [&](uint32_t k) -> uint32_t {
     if (k < nw && k >= avail) {
+      Spin sp;
       for (;;) {
         avail = lds_acquire(&s_misc.avail[L]);
         if (k < avail) break;
-        __builtin_amdgcn_s_sleep(1);
+        if (!sp.pause()) {
+          avail = kDone;  // give up waiting: the lane decodes to an error and stops
+          break;
+        }
       }
     }
     const uint32_t w = ring_base[((k >> 2) & (kRows - 1)) * (4 * kLanes) + (k & 3)];
@@ -545,26 +579,6 @@ __device__ __forceinline__ uint4 lit_read16(uint32_t p) {
   return v;
 }
 
-// Flush window bytes [flushed, upto) to HBM: whole 16-byte chunks once at
-// least 1 KiB is pending (and everything when final).
-__device__ __forceinline__ void flush_window(GMEM uint8_t* out, uint32_t& flushed, uint32_t upto, bool final_flush,
-                                             uint32_t lane, uint32_t raw_len) {
-  const uint8_t* ring = ring_ptr();
-  upto = min(upto, raw_len);  // never past the block's output
-  if (!final_flush && upto - flushed < 1024) return;
-  const uint32_t end = final_flush ? upto : (upto & ~15u);
-  for (uint32_t p = flushed + lane * 16; p < end; p += 1024) {
-    if (p + 16 <= end) {
-      uint4 v;
-      __builtin_memcpy(&v, ring + (p & kRingMask), 16);
-      gstore16(out + p, v);
-    } else {
-      for (uint32_t q = p; q < end; q++) out[q] = ring[q & kRingMask];
-    }
-  }
-  flushed = end;
-}
-
 // Window/ring accesses that are known not to wrap (the common case).
 __device__ __forceinline__ void write_upto16(uint8_t* d, uint4 v, uint32_t n) {
   if (n == 16) {
@@ -627,60 +641,124 @@ struct LzArgs {
   GMEM uint8_t* rounds;
 };
 
-// Fetcher side of A3-A6: stream records (1 KiB = 128 records per copy) and
-// literal bytes (1 KiB per copy) into their LDS rings, at most one ring ahead
-// of what the resolver has consumed.
+// Resolution runs as a pipeline over groups of 64 sequences.  Resolver
+// wavefront w takes groups w, w + kRes, w + 2 kRes, ...; everything a group
+// needs that does not depend on earlier groups' output (its records, the two
+// prefix sums, its literal strings) is done ahead, and only the copies of its
+// back-references wait until every earlier group is final.  Progress is
+// handed over through LDS counters:
+//   rec_avail / lit_avail  fetcher -> resolvers: records / literal bytes staged
+//   g_out / g_lit          fetcher -> resolvers: output and literal offsets of
+//                          each staged group (ring of kGRing groups)
+//   next_group[w]          resolver w -> fetcher: records, offsets and literals
+//                          of w's groups before this index are no longer read
+//   done_upto              resolvers: output bytes below are final
+//   flushed                flusher: output bytes below are in HBM
+// The output window holds positions [low, low + kRing) with
+// low = min(done_upto - 32768, flushed): every source a pending copy can
+// name lies at or above done_upto - 32768, and slots below flushed are free.
+
+// Fetcher side: stream records (1 KiB = 128 records = 2 groups per copy) and
+// literal bytes (1 KiB per copy) into their LDS rings, and compute the offsets
+// of each group from its records once they arrive.
+template <int kRes>
 __device__ void fetch_tokens(const LzArgs& a) {
   const uint32_t lane = lane_id();
   const uint32_t rec_chunks = (a.n_seq + 127) / 128, lit_chunks = (a.n_lit + 1023) / 1024;
   const uint64_t lit_base = 8ull * a.n_seq;
-  uint32_t rf = 0, lf = 0;
+  uint32_t rf = 0, lf = 0, tf = 0, carry_out = 0, carry_lit = 0;
+  Spin sp;
   while (rf < rec_chunks || lf < lit_chunks) {
-    const uint32_t rc = lds_acquire(&s_misc.rec_cons), lc = lds_acquire(&s_misc.lit_cons);
-    if (rc == kDone && lc == kDone) break;  // the resolver has finished
+    uint32_t gmin = kDone;
+#pragma unroll
+    for (int w = 0; w < kRes; w++) gmin = min(gmin, lds_acquire(&s_misc.next_group[w]));
+    if (gmin == kDone) break;  // every resolver has finished
+    // literal bytes before the first group still being read are consumed
+    const uint32_t lit_cons = gmin < 2 * tf ? s_misc.g_lit[gmin % kGRing] : carry_lit;
     uint32_t issued = 0;
-    while (rf < rec_chunks && (rc == kDone || 128 * (rf + 1) <= rc + kRecRing) && issued < 8) {
+    while (rf < rec_chunks && 128ull * (rf + 1) <= 64ull * gmin + kRecRing && issued < 8) {
       uint64_t o = 1024ull * rf + 16 * lane;
       if (o + 16 > a.ws_len) o = a.ws_len - 16;
       dma16(a.ws + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
       rf++;
       issued++;
     }
-    while (lf < lit_chunks && (lc == kDone || 1024 * (lf + 1) <= lc + kLitRing) && issued < 12) {
+    while (lf < lit_chunks && 1024ull * (lf + 1) <= (uint64_t)lit_cons + kLitRing && issued < 12) {
       uint64_t o = lit_base + 1024ull * lf + 16 * lane;
       if (o + 16 > a.ws_len) o = a.ws_len - 16;
       dma16(a.ws + o, &lit_ring()[1024 * (lf % (kLitRing / 1024))]);
       lf++;
       issued++;
     }
-    if (issued) {
-      wait_all_memory();
-      lds_release(&s_misc.lit_avail, min(a.n_lit, 1024 * lf));
-      lds_release(&s_misc.rec_avail, min(a.n_seq, 128 * rf));
-    } else {
-      __builtin_amdgcn_s_sleep(2);
+    if (!issued) {
+      if (!sp.pause()) return;
+      continue;
     }
+    sp = Spin();
+    wait_all_memory();
+    // offsets of the two groups of every record chunk that arrived
+    for (; tf < rf; tf++) {
+      const uint32_t j = 128 * tf + 2 * lane;
+      const uint2 r0 = j < a.n_seq ? rec_ring()[j % kRecRing] : make_uint2(0u, 0u);
+      const uint2 r1 = j + 1 < a.n_seq ? rec_ring()[(j + 1) % kRecRing] : make_uint2(0u, 0u);
+      const uint32_t il = wave_incl_scan(r0.x + r1.x);
+      const uint32_t io = wave_incl_scan(r0.x + (r0.y & 0xFFFFu) + r1.x + (r1.y & 0xFFFFu));
+      const uint32_t l31 = readlane(il, 31), o31 = readlane(io, 31);
+      if (lane == 0) {
+        s_misc.g_out[(2 * tf) % kGRing] = carry_out;
+        s_misc.g_lit[(2 * tf) % kGRing] = carry_lit;
+        s_misc.g_out[(2 * tf + 1) % kGRing] = carry_out + o31;
+        s_misc.g_lit[(2 * tf + 1) % kGRing] = carry_lit + l31;
+      }
+      carry_out += readlane(io, 63);
+      carry_lit += readlane(il, 63);
+    }
+    lds_release(&s_misc.lit_avail, min(a.n_lit, 1024 * lf));
+    lds_release(&s_misc.rec_avail, min(a.n_seq, 128 * rf));
   }
 }
 
-// Resolver: groups of 64 sequences, one per lane.
-__device__ void resolve_block(const LzArgs& a) {
+// Wait until output positions below `end` may be written (see above);
+// false if the wait was abandoned.
+__device__ __forceinline__ bool wait_window(uint32_t end) {
+  Spin sp;
+  for (;;) {
+    const uint32_t done = lds_acquire(&s_misc.done_upto), fl = lds_acquire(&s_misc.flushed);
+    const uint32_t low = min(done > 32768u ? done - 32768u : 0u, fl);
+    if (end <= low + kRing) return true;
+    if (!sp.pause()) return false;
+  }
+}
+// Wait until *p >= v; false if the wait was abandoned.
+__device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t v, uint32_t& seen) {
+  Spin sp;
+  for (;;) {
+    seen = lds_acquire(p);
+    if (seen >= v) return true;
+    if (!sp.pause()) return false;
+  }
+}
+__device__ __forceinline__ bool wait_done(uint32_t pos) {
+  uint32_t seen;
+  return wait_at_least(&s_misc.done_upto, pos, seen);
+}
+
+// Resolver wavefront w of kRes.
+template <int kRes>
+__device__ void resolve_groups(const LzArgs& a, uint32_t w) {
   uint8_t* ring = ring_ptr();
   const uint32_t lane = lane_id();
   const GMEM uint8_t* lits = a.ws + 8ull * a.n_seq;
-  uint32_t carry_lit = 0, carry_out = 0, flushed = 0;
   uint32_t rec_avail = 0, lit_avail = 0;
   const uint32_t n_groups = (a.n_seq + 63) / 64;
-  for (uint32_t g = 0; g < n_groups; g++) {
+  for (uint32_t g = w; g < n_groups; g += kRes) {
     const uint32_t g0 = g * 64;
     const uint32_t need = min(a.n_seq, g0 + 64);
-    while (rec_avail < need) {
-      rec_avail = lds_acquire(&s_misc.rec_avail);
-      if (rec_avail < need) __builtin_amdgcn_s_sleep(1);
-    }
+    if (rec_avail < need && !wait_at_least(&s_misc.rec_avail, need, rec_avail)) break;
     const uint32_t j = g0 + lane;
     const bool valid = j < a.n_seq;
     const uint2 rec = valid ? rec_ring()[j % kRecRing] : make_uint2(0u, 0u);
+    const uint32_t g_out = s_misc.g_out[g % kGRing], g_lit = s_misc.g_lit[g % kGRing];
     uint32_t L = rec.x;
     const uint32_t M = rec.y & 0xFFFFu;
     const uint32_t D = rec.y >> 16;
@@ -688,37 +766,38 @@ __device__ void resolve_block(const LzArgs& a) {
     const uint32_t inc_lit = wave_incl_scan(L);
     const uint32_t inc_out = wave_incl_scan(L + M);
     const uint32_t tot_lit = readlane(inc_lit, 63);
-    uint32_t lsrc = carry_lit + inc_lit - L;
-    uint32_t pos = carry_out + inc_out - (L + M);
+    uint32_t lsrc = g_lit + inc_lit - L;
+    uint32_t pos = g_out + inc_out - (L + M);
     const uint32_t end = pos + L + M;
     const uint32_t m_cnt = min(64u, a.n_seq - g0);
+    const uint32_t g_end = g_out + readlane(inc_out, 63);
     // literals come from the LDS ring unless the group holds more than half of it
     const bool lits_staged = tot_lit <= kLitStagedMax;
-    if (lits_staged && tot_lit) {
-      while (lit_avail < carry_lit + tot_lit) {
-        lit_avail = lds_acquire(&s_misc.lit_avail);
-        if (lit_avail < carry_lit + tot_lit) __builtin_amdgcn_s_sleep(1);
-      }
-    }
+    if (lits_staged && tot_lit && lit_avail < g_lit + tot_lit &&
+        !wait_at_least(&s_misc.lit_avail, g_lit + tot_lit, lit_avail))
+      break;
     uint32_t rounds = 0;
     bool split = false;
     // fast path: no copy of the group wraps around the window or the literal
     // ring, none overlaps its own output, and the group fits the window
-    const uint32_t g_end = readlane(end, m_cnt - 1);
     const uint32_t src0 = pos + L - D;
     const bool lane_ok =
         !valid || ((pos & kRingMask) + L + M <= kRing &&
                    (M == 0 || (D >= M && (src0 & kRingMask) + ((M + 15) & ~15u) <= kRing)) &&
                    (L == 0 || (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing));
-    const bool fast = lits_staged && g_end - readlane(pos, 0) <= kSpanCap && !__ballot(!lane_ok);
+    const bool fast = lits_staged && g_end - g_out <= kSpanCap && !__ballot(!lane_ok);
     if (fast) {
+      if (!wait_window(g_end)) break;
+      // A4: literal strings into the window, ahead of earlier groups
       if (valid && L) {
         uint8_t* d = ring + (pos & kRingMask);
         const uint8_t* q = lit_ring() + (lsrc & (kLitRing - 1));
         for (uint32_t k = 0; k < L; k += 16) write_upto16(d + k, read16(q + k), min(16u, L - k));
       }
+      lds_release(&s_misc.next_group[w], g + kRes);
       const uint32_t dst = pos + L;
       bool pending = valid && M > 0;
+      if (!wait_done(g_out)) break;
       if (a.single_pass) {
         // A6: no back-reference of the group depends on another (DE)
         if (__ballot(pending)) rounds = 1;
@@ -736,18 +815,26 @@ __device__ void resolve_block(const LzArgs& a) {
           rounds++;
         }
       }
-      flush_window(a.out, flushed, g_end, false, lane, a.raw_len);
+      lds_release(&s_misc.done_upto, g_end);
     } else {
+      // general path, after every earlier group is final: the group is
+      // resolved in pieces that fit the window, a literal run longer than the
+      // window is streamed through it first
+      if (!wait_done(g_out)) break;
       uint32_t lo = 0;
-      while (lo < m_cnt) {
+      bool ok = true;
+      while (ok && lo < m_cnt) {
         uint32_t base = readlane(pos, lo);
         {
-          // a literal run too long for the window is streamed through it first
           uint32_t Llo = readlane(L, lo), Mlo = readlane(M, lo), slo = readlane(lsrc, lo);
           while (Llo + Mlo > kSpanCap) {
             const uint32_t P = kSpanCap / 2;
+            if (!wait_window(base + P)) {
+              ok = false;
+              break;
+            }
             stream_lits_hbm(lits + slo, base, P, lane);
-            flush_window(a.out, flushed, base + P, false, lane, a.raw_len);
+            lds_release(&s_misc.done_upto, base + P);
             base += P;
             slo += P;
             Llo -= P;
@@ -763,6 +850,11 @@ __device__ void resolve_block(const LzArgs& a) {
         const uint32_t hi = lo + (uint32_t)__popcll(fit);
         if (hi < m_cnt) split = true;
         const bool active = lane >= lo && lane < hi;
+        const uint32_t piece_end = readlane(end, hi - 1);
+        if (!ok || !wait_window(piece_end)) {
+          ok = false;
+          break;
+        }
         // A4: literal strings into the window
         if (active && L) {
           if (lits_staged) {
@@ -791,19 +883,44 @@ __device__ void resolve_block(const LzArgs& a) {
             rounds++;
           }
         }
-        flush_window(a.out, flushed, readlane(end, hi - 1), false, lane, a.raw_len);
+        lds_release(&s_misc.done_upto, piece_end);
         lo = hi;
       }
+      if (!ok) break;
+      lds_release(&s_misc.next_group[w], g + kRes);
     }
     if (a.rounds && lane == 0) a.rounds[g] = (uint8_t)(min(rounds, 127u) | (split ? 0x80u : 0u));
-    carry_lit += tot_lit;
-    carry_out += readlane(inc_out, 63);
-    lds_release(&s_misc.lit_cons, carry_lit);
-    lds_release(&s_misc.rec_cons, min(a.n_seq, g0 + 64));
   }
-  flush_window(a.out, flushed, a.raw_len, true, lane, a.raw_len);
-  lds_release(&s_misc.lit_cons, kDone);
-  lds_release(&s_misc.rec_cons, kDone);
+  lds_release(&s_misc.next_group[w], kDone);
+}
+
+// Flusher wavefront: final window bytes to HBM, 16 bytes per lane per store,
+// once at least 1 KiB is final (and the rest at the end).
+__device__ void flush_output(const LzArgs& a) {
+  const uint8_t* ring = ring_ptr();
+  const uint32_t lane = lane_id();
+  uint32_t fl = 0;
+  Spin sp;
+  while (fl < a.raw_len) {
+    const uint32_t done = min(lds_acquire(&s_misc.done_upto), a.raw_len);
+    const uint32_t end = done == a.raw_len ? done : (done & ~15u);
+    if (end <= fl || (end - fl < 1024 && end != a.raw_len)) {
+      if (!sp.pause()) return;
+      continue;
+    }
+    sp = Spin();
+    for (uint32_t p = fl + lane * 16; p < end; p += 1024) {
+      if (p + 16 <= end) {
+        uint4 v;
+        __builtin_memcpy(&v, ring + (p & kRingMask), 16);
+        gstore16(a.out + p, v);
+      } else {
+        for (uint32_t q = p; q < end; q++) a.out[q] = ring[q & kRingMask];
+      }
+    }
+    fl = end;
+    lds_release(&s_misc.flushed, fl);
+  }
 }
 
 // ---------------------------------------------------------------- kernel
@@ -816,11 +933,14 @@ __device__ __forceinline__ void stamp(const DevJob& job, int i) {
 // kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR or GMPK_MODE_DE.
 template <int kDec, int kMode>
 __device__ void inflate_block(const DevJob& job, uint32_t flags) {
-  constexpr uint32_t kThreads = 64 * (kDec + 1), kLanes = 64 * kDec;
+  constexpr uint32_t kThreads = 64 * (kDec + 2), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
   stamp(job, 0);
-  if (t == 0) sh.err = 0;
+  if (t == 0) {
+    sh.err = 0;
+    sh.abort = 0;
+  }
   __syncthreads();
   const GMEM uint8_t* blk = gmem(job.comp);
   GMEM int32_t* status = gmem(job.status);
@@ -942,12 +1062,13 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   if (t == 0 && (carry[0] * 4ull != payload || carry[1] != n_seq || carry[2] != n_lit || carry[3] != raw_len))
     set_err(kEFORMAT);
   __syncthreads();  // workspace writes of all lanes are visible after this barrier
-  if (sh.err) {
-    if (t == 0) *status = sh.err;
+  if (sh.err || sh.abort) {
+    if (t == 0) *status = sh.abort ? kESTALL : sh.err;
     return;
   }
   stamp(job, 2);
-  // ---- A3-A6: decoder wavefront 0 resolves, the fetcher stages tokens
+  // ---- A3-A6: the decoder wavefronts resolve, the fetcher stages tokens,
+  // the last wavefront writes the output
   LzArgs a;
   a.ws = gmem(job.ws);
   a.ws_len = job.ws_len;
@@ -960,21 +1081,25 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   if (t == 0) {
     sh.rec_avail = 0;
     sh.lit_avail = 0;
-    sh.rec_cons = 0;
-    sh.lit_cons = 0;
+    sh.done_upto = 0;
+    sh.flushed = 0;
   }
+  if (t < kMaxDecWaves) sh.next_group[t] = t < kDec ? t : kDone;
   __syncthreads();
   if (wave == kDec) {
-    fetch_tokens(a);
-  } else if (wave == 0) {
-    resolve_block(a);
-    stamp(job, 3);
-    if (t == 0) *status = kOK;
+    fetch_tokens<kDec>(a);
+  } else if (wave == kDec + 1) {
+    flush_output(a);
+  } else {
+    resolve_groups<kDec>(a, wave);
   }
+  __syncthreads();
+  stamp(job, 3);
+  if (t == 0) *status = sh.abort ? kESTALL : kOK;
 }
 
 template <int kDec, int kMode>
-__global__ __launch_bounds__(64 * (kDec + 1)) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
+__global__ __launch_bounds__(64 * (kDec + 2)) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
                                                                   uint32_t flags) {
   if (blockIdx.x >= n_jobs) return;
   DevJob job = jobs[blockIdx.x];
@@ -986,7 +1111,7 @@ __global__ __launch_bounds__(64 * (kDec + 1)) void inflate_kernel(const DevJob* 
 // the job table is exhausted; every workgroup exits once it draws an index
 // past the end.
 template <int kDec, int kMode>
-__global__ __launch_bounds__(64 * (kDec + 1)) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
+__global__ __launch_bounds__(64 * (kDec + 2)) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
                                                                              uint32_t n_jobs, uint32_t flags,
                                                                              uint32_t* __restrict__ queue) {
   for (;;) {
@@ -1010,10 +1135,10 @@ void launch_one(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t 
                 uint32_t* d_queue, hipStream_t stream) {
   if (persistent) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, d_queue);
-    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(64 * (kDec + 1)), 0, stream,
+    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(64 * (kDec + 2)), 0, stream,
                        d_jobs, n_jobs, flags, d_queue);
   } else {
-    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(64 * (kDec + 1)), 0, stream, d_jobs, n_jobs,
+    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(64 * (kDec + 2)), 0, stream, d_jobs, n_jobs,
                        flags);
   }
 }

@@ -50,3 +50,11 @@ def test_host_parser_rejects_bad_headers(hip_lib_built):
             gmp.block_info(bytes(b))
         assert e.value.status == gmp.EFORMAT
     assert gmp.strerror(gmp.ESUB)
+
+
+def test_stream_info_long_block_table(hip_lib_built):
+    # 768 blocks: the block table alone is longer than 4 KiB
+    import paper_1606_00519_amd as gmp
+    data = synth.csv_rows(3 << 20).tobytes()
+    s = oracle.compress(data, oracle.CompressParams(block_size=4096, sub_target_raw=1024))
+    assert gmp.stream_info(s) == (768, 4096, len(data))
