@@ -340,7 +340,7 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
                      "status": torch.full((nb,), 99, dtype=torch.int32, device="cuda"), "raw": raw})
     torch.cuda.synchronize()
     mean_u = float(np.mean([len(r) for r in raws]))
-    srv = gmp.Server(ctx, budget_bytes=budget, slots=16)
+    srv = gmp.Server(ctx, budget_bytes=budget, slots=4, waves=4)
     rng = np.random.default_rng(synth.SERVE_SEED + 100)
     levels = []
     for rho in (0.1, 0.3, 0.5, 0.7, 0.9):
@@ -376,8 +376,9 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
     for e in pool:
         if not np.all(e["status"].cpu().numpy() == 0) or e["out"].cpu().numpy().tobytes() != e["raw"]:
             raise RuntimeError("serve: a pooled request's output differs from its source bytes")
-    return {"pool_requests": n_pool, "mean_request_bytes": int(mean_u), "budget_bytes": budget, "slots": 16,
-            "peak_in_flight_bytes": info["peak_in_flight_bytes"], "peak_concurrent": info["peak_slots"],
+    return {"pool_requests": n_pool, "mean_request_bytes": int(mean_u), "budget_bytes": budget, "slots": 4,
+            "launches": info["launches"], "peak_in_flight_bytes": info["peak_in_flight_bytes"],
+            "peak_concurrent_launches": info["peak_slots"],
             "reference_peak_GBps": round(peak_gbps, 3), "levels": levels}
 
 

@@ -181,18 +181,21 @@ gmp_status gmp_autotune(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, uint32_t
 
 /* ---- request loop (continuous batching on one GPU) ------------------------------ */
 /* A server admits decompression requests of mixed sizes as they arrive and runs
- * them concurrently: a scheduler thread admits requests first come first served
+ * them concurrently.  A scheduler thread admits requests first come first served
  * while the bytes of everything in flight (compressed + decompressed + token
- * workspace) stay within `budget_bytes` and one of `n_slots` execution slots
- * (a HIP stream each, default priority) is free, launches each admitted
- * request's blocks on its slot (one workgroup per block; blocks are
- * independent, section "Gompresso Overview"), and on completion frees budget,
- * workspace and slot and admits the next ones.  Work of requests admitted at
- * different times overlaps on the device.  Compressed input, output and status
- * words belong to the caller and stay resident on the device; the server owns a
+ * workspace) stay within `budget_bytes`; whenever one of its `n_slots` launch
+ * slots (a HIP stream each, default priority) is free, it launches every
+ * admitted request that is not running yet as one kernel over all their blocks
+ * (one workgroup per block, largest first; blocks are independent, section
+ * "Gompresso Overview").  Requests that arrive while others run join the next
+ * launch, and launches of different slots overlap on the device.  When a launch
+ * completes, its requests are reported and their budget is released.  Every
+ * block is decoded in the mode its header names (GMP_MODE_AUTO); a request's
+ * flags are checked at submission.  Compressed input, output and status words
+ * belong to the caller and stay resident on the device; the server owns a
  * token-workspace arena of `workspace_bytes` (0 = budget / 2), handed out
- * first-fit.  A request whose bytes exceed the budget can never be admitted
- * and is refused by gmp_server_submit with GMP_EBUSY. */
+ * first-fit.  A request whose bytes exceed the budget can never be admitted and
+ * is refused by gmp_server_submit with GMP_EBUSY. */
 typedef struct gmp_server gmp_server;
 
 typedef struct {
@@ -219,14 +222,17 @@ typedef struct {
 typedef struct {
   uint64_t submitted, finished, pending;
   uint64_t in_flight_bytes, peak_in_flight_bytes, budget;
-  uint32_t peak_slots, reserved;
+  uint64_t launches;        /* kernel launches so far (each covers every request admitted since the last) */
+  uint32_t peak_slots;      /* most launches in flight at once */
+  uint32_t reserved;
 } gmp_server_info;
 
 gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uint64_t workspace_bytes, uint32_t n_slots,
                              const gmp_tuning* tuning, gmp_server** out);
 /* Queue a request (thread-safe).  The header and block table are checked here:
- * EFORMAT / ESIZE / EINVAL as for gmp_decompress_stream; EBUSY if the request
- * alone exceeds the budget. */
+ * EFORMAT / ESIZE / EINVAL as for gmp_decompress_stream (GMP_MODE_DE on a block
+ * whose header is not DE with a group that is a multiple of 64 is EINVAL); EBUSY
+ * if the request alone exceeds the budget. */
 gmp_status gmp_server_submit(gmp_server* srv, const gmp_request* req);
 /* Move up to `max` completions (in completion order) to `out`; returns how many. */
 uint32_t gmp_server_poll(gmp_server* srv, gmp_completion* out, uint32_t max);

@@ -64,7 +64,7 @@ class Completion(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("finished", C.c_uint64), ("pending", C.c_uint64),
                 ("in_flight_bytes", C.c_uint64), ("peak_in_flight_bytes", C.c_uint64), ("budget", C.c_uint64),
-                ("peak_slots", C.c_uint32), ("reserved", C.c_uint32)]
+                ("launches", C.c_uint64), ("peak_slots", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Tuning(C.Structure):
@@ -217,8 +217,8 @@ class Server:
     of the stream (for its headers), an output tensor and a per-block int32 status
     tensor; the caller keeps them alive until the request's completion is polled."""
 
-    def __init__(self, ctx: "Context", budget_bytes: int, workspace_bytes: int = 0, slots: int = 8,
-                 waves: int = 1):
+    def __init__(self, ctx: "Context", budget_bytes: int, workspace_bytes: int = 0, slots: int = 4,
+                 waves: int = 4):
         self.ctx = ctx
         t = Tuning(waves, 0, 0, 0)
         h = C.c_void_p()

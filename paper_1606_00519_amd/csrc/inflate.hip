@@ -141,6 +141,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
+// Inclusive prefix maximum over the 64 lanes (same DPP pattern).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+  return x;
+}
 
 // LDS progress counters: release after the data they announce, acquire before
 // reading that data.
@@ -610,7 +620,7 @@ __device__ __forceinline__ uint4 read16(const uint8_t* p) {
   __builtin_memcpy(&v, p, 16);
   return v;
 }
-// copy len bytes (dst - src >= len, or >= 16) inside the window, no wrap
+// copy len bytes (dst - src >= len) inside the window, no wrap
 __device__ __forceinline__ void copy_nowrap(uint8_t* ring, uint32_t dst, uint32_t src, uint32_t len) {
   uint8_t* d = ring + (dst & kRingMask);
   const uint8_t* q = ring + (src & kRingMask);
@@ -796,25 +806,39 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       }
       lds_release(&s_misc.next_group[w], g + kRes);
       const uint32_t dst = pos + L;
-      bool pending = valid && M > 0;
-      if (!wait_done(g_out)) break;
+      const bool has = valid && M > 0;
+      const uint32_t need_end = src0 + M;  // no overlap on this path: the source is [src0, src0 + M)
+      // Round membership depends only on positions.  A6 (DE): every
+      // back-reference of the group in the one pass.  A5 (MRR): round r takes
+      // the pending lanes whose source ends at or below the destination of the
+      // lowest pending lane.  It is worked out first, in registers; the copies
+      // then run round after round (a wavefront's LDS accesses stay in order,
+      // so each round reads what the earlier ones wrote).
+      uint32_t my_round = has ? 1u : 0u;
       if (a.single_pass) {
-        // A6: no back-reference of the group depends on another (DE)
-        if (__ballot(pending)) rounds = 1;
-        if (pending) copy_nowrap(ring, dst, src0, M);
+        rounds = __ballot(has) ? 1u : 0u;
       } else {
-        // A5: Multi-Round Resolution
-        const uint32_t need_end = src0 + M;  // no overlap: the source is [src0, src0 + M)
+        bool pending = has;
         for (;;) {
           const uint64_t votes = __ballot(pending);
           if (votes == 0) break;
+          rounds++;
           const uint32_t hwm = readlane(dst, (uint32_t)__builtin_ctzll(votes));
           const bool can = pending && need_end <= hwm;
-          if (can) copy_nowrap(ring, dst, src0, M);
+          my_round = can ? rounds : my_round;
           pending = pending && !can;
-          rounds++;
         }
       }
+      // The only bytes the group reads that it does not write itself lie
+      // below g_out: it copies as soon as those it needs are final, possibly
+      // before the groups in front of it have finished.
+      const uint32_t need = min(readlane(wave_incl_max(has ? need_end : 0u), 63), g_out);
+      if (!wait_done(need)) break;
+      for (uint32_t r = 1; r <= rounds; r++) {
+        if (my_round == r) copy_nowrap(ring, dst, src0, M);
+      }
+      // its output is final once everything in front of it is
+      if (!wait_done(g_out)) break;
       lds_release(&s_misc.done_upto, g_end);
     } else {
       // general path, after every earlier group is final: the group is

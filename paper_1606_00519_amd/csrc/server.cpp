@@ -2,12 +2,16 @@
 // decompression requests on one GPU.
 //
 // Requests arrive at any time from any host thread.  A scheduler thread
-// admits them first-come first-served while the bytes of everything in
+// admits them first come first served while the bytes of everything in
 // flight (compressed + decompressed + token workspace) stay within the
-// budget and an execution slot is free, launches each admitted request's
-// blocks on that slot's stream (so the work of requests admitted at
-// different times overlaps on the device), watches the slots' events, and
-// on completion releases budget, workspace and slot and admits more.
+// budget, and whenever one of its launch slots is free it launches every
+// admitted request not yet running as ONE kernel over all their blocks
+// (largest blocks first), on that slot's stream.  Requests that arrive while
+// others run join the next launch; launches of different slots overlap on
+// the device.  (One launch per request would leave the device mostly idle:
+// a request has only a handful of blocks, and the runtime runs few kernels
+// at once.)  When a launch completes, its requests' budget and workspace are
+// released and more are admitted.
 //
 // Token workspace comes from one device arena owned by the server, handed
 // out first-fit in 256-byte units; everything else (compressed input,
@@ -16,6 +20,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <algorithm>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -92,8 +97,8 @@ class Arena {
 
 struct Request {
   gmp_request r;
-  std::vector<gmpk::DevJob> jobs;  // device pointers filled in at admission, except ws
-  uint64_t ws_bytes = 0, bytes = 0, t_submit = 0;
+  std::vector<gmpk::DevJob> jobs;  // device pointers filled in at submission, except ws
+  uint64_t ws_bytes = 0, bytes = 0, t_submit = 0, ws_off = 0;
 };
 
 struct Slot {
@@ -103,8 +108,8 @@ struct Slot {
   gmpk::DevJob* h_jobs = nullptr;  // pinned
   size_t cap = 0;
   bool busy = false;
-  Request req;
-  uint64_t ws_off = 0, t_admit = 0;
+  std::vector<Request> reqs;  // requests of the running launch
+  uint64_t t_launch = 0;
 };
 
 }  // namespace
@@ -119,8 +124,9 @@ struct gmp_server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request> pending;  // submitted, not admitted (guarded by mu)
+  std::vector<Request> ready;   // admitted, waiting for a launch slot
   std::vector<gmp_completion> completed;  // guarded by mu
-  uint64_t in_flight_bytes = 0, peak_bytes = 0, submitted = 0, finished = 0;
+  uint64_t in_flight_bytes = 0, peak_bytes = 0, submitted = 0, finished = 0, launches = 0;
   uint32_t peak_slots = 0;
   int32_t error = GMP_OK;  // first device error of the scheduler
   std::atomic<bool> stop{false};
@@ -129,100 +135,118 @@ struct gmp_server {
 
 namespace {
 
+void complete(gmp_server* s, const Request& rq, int32_t status, uint64_t t_launch) {
+  gmp_completion c{};
+  c.tag = rq.r.tag;
+  c.status = status;
+  c.t_submit_ns = rq.t_submit;
+  c.t_admit_ns = t_launch;
+  c.t_done_ns = now_ns();
+  c.bytes = rq.r.out_len;
+  s->completed.push_back(c);
+  s->finished++;
+}
+
+// Launch every ready request as one kernel on slot `sl`.
+gmp_status launch_ready(gmp_server* s, Slot& sl) {
+  size_t n = 0;
+  for (const Request& rq : s->ready) n += rq.jobs.size();
+  if (n > sl.cap) {
+    if (sl.d_jobs) (void)hipFree(sl.d_jobs);
+    if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+    sl.d_jobs = nullptr;
+    sl.h_jobs = nullptr;
+    sl.cap = 0;
+    const size_t cap = n + n / 2 + 16;
+    if (hipMalloc(&sl.d_jobs, cap * sizeof(gmpk::DevJob)) != hipSuccess ||
+        hipHostMalloc(&sl.h_jobs, cap * sizeof(gmpk::DevJob), hipHostMallocDefault) != hipSuccess)
+      return GMP_ENOMEM;
+    sl.cap = cap;
+  }
+  size_t k = 0;
+  for (const Request& rq : s->ready) {
+    uint64_t o = rq.ws_off;
+    for (const gmpk::DevJob& j : rq.jobs) {
+      sl.h_jobs[k] = j;
+      sl.h_jobs[k].ws = s->d_arena + o;
+      o += j.ws_len;
+      k++;
+    }
+  }
+  // largest blocks first, so the long ones start early
+  std::stable_sort(sl.h_jobs, sl.h_jobs + n,
+                   [](const gmpk::DevJob& x, const gmpk::DevJob& y) { return x.out_len > y.out_len; });
+  if (n) {
+    if (hipMemcpyAsync(sl.d_jobs, sl.h_jobs, n * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, sl.stream) !=
+            hipSuccess ||
+        gmpk_launch(sl.d_jobs, (uint32_t)n, GMP_MODE_AUTO, s->tuning.waves_per_block, 0, 0, nullptr, sl.stream) != 0)
+      return GMP_EDEVICE;
+  }
+  if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return GMP_EDEVICE;
+  return GMP_OK;
+}
+
 // Scheduler thread body.
 void serve(gmp_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop.load()) {
     bool progress = false;
-    // completions
+    // completed launches: their requests finish, budget and workspace return
     for (Slot& sl : s->slots) {
       if (!sl.busy) continue;
       const hipError_t q = hipEventQuery(sl.done);
       if (q == hipErrorNotReady) continue;
-      gmp_completion c{};
-      c.tag = sl.req.r.tag;
-      c.status = q == hipSuccess ? GMP_OK : GMP_EDEVICE;
-      c.t_submit_ns = sl.req.t_submit;
-      c.t_admit_ns = sl.t_admit;
-      c.t_done_ns = now_ns();
-      c.bytes = sl.req.r.out_len;
-      if (sl.req.ws_bytes) s->arena->release(sl.ws_off, sl.req.ws_bytes);
-      s->in_flight_bytes -= sl.req.bytes;
+      for (const Request& rq : sl.reqs) {
+        complete(s, rq, q == hipSuccess ? GMP_OK : GMP_EDEVICE, sl.t_launch);
+        if (rq.ws_bytes) s->arena->release(rq.ws_off, rq.ws_bytes);
+        s->in_flight_bytes -= rq.bytes;
+      }
+      if (q != hipSuccess && s->error == GMP_OK) s->error = GMP_EDEVICE;
+      sl.reqs.clear();
       sl.busy = false;
-      s->completed.push_back(c);
-      s->finished++;
       progress = true;
     }
-    // admissions, first come first served
+    // admissions, first come first served, within the budget and the arena
     while (!s->pending.empty()) {
       Request& rq = s->pending.front();
       if (s->in_flight_bytes + rq.bytes > s->budget) break;
-      Slot* free_slot = nullptr;
-      for (Slot& sl : s->slots)
-        if (!sl.busy) {
-          free_slot = &sl;
-          break;
-        }
-      if (!free_slot) break;
-      uint64_t ws_off = 0;
-      if (rq.ws_bytes && !s->arena->alloc(rq.ws_bytes, &ws_off)) break;
-      Slot& sl = *free_slot;
-      const size_t n = rq.jobs.size();
-      gmp_status st = GMP_OK;
-      if (n > sl.cap) {
-        if (sl.d_jobs) (void)hipFree(sl.d_jobs);
-        if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
-        sl.d_jobs = nullptr;
-        sl.h_jobs = nullptr;
-        sl.cap = 0;
-        if (hipMalloc(&sl.d_jobs, n * sizeof(gmpk::DevJob)) != hipSuccess ||
-            hipHostMalloc(&sl.h_jobs, n * sizeof(gmpk::DevJob), hipHostMallocDefault) != hipSuccess)
-          st = GMP_ENOMEM;
-        else
-          sl.cap = n;
-      }
-      if (st == GMP_OK) {
-        uint64_t o = ws_off;
-        for (size_t k = 0; k < n; k++) {
-          sl.h_jobs[k] = rq.jobs[k];
-          sl.h_jobs[k].ws = s->d_arena + o;
-          o += sl.h_jobs[k].ws_len;
-        }
-        if (hipMemcpyAsync(sl.d_jobs, sl.h_jobs, n * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, sl.stream) !=
-                hipSuccess ||
-            gmpk_launch(sl.d_jobs, (uint32_t)n, rq.r.flags, s->tuning.waves_per_block, 0, 0, nullptr,
-                        sl.stream) != 0 ||
-            hipEventRecord(sl.done, sl.stream) != hipSuccess)
-          st = GMP_EDEVICE;
-      }
-      if (st != GMP_OK) {
-        // the request fails; its budget was never taken
-        if (rq.ws_bytes) s->arena->release(ws_off, rq.ws_bytes);
-        gmp_completion c{};
-        c.tag = rq.r.tag;
-        c.status = st;
-        c.t_submit_ns = rq.t_submit;
-        c.t_admit_ns = c.t_done_ns = now_ns();
-        c.bytes = rq.r.out_len;
-        s->completed.push_back(c);
-        s->finished++;
-        if (s->error == GMP_OK) s->error = st;
-        s->pending.pop_front();
-        progress = true;
-        continue;
-      }
-      sl.busy = true;
-      sl.ws_off = ws_off;
-      sl.t_admit = now_ns();
-      sl.req = std::move(rq);
-      s->pending.pop_front();
-      s->in_flight_bytes += sl.req.bytes;
+      if (rq.ws_bytes && !s->arena->alloc(rq.ws_bytes, &rq.ws_off)) break;
+      s->in_flight_bytes += rq.bytes;
       if (s->in_flight_bytes > s->peak_bytes) s->peak_bytes = s->in_flight_bytes;
-      uint32_t busy = 0;
-      for (Slot& x : s->slots) busy += x.busy ? 1u : 0u;
-      if (busy > s->peak_slots) s->peak_slots = busy;
+      s->ready.push_back(std::move(rq));
+      s->pending.pop_front();
       progress = true;
+    }
+    // one launch for everything admitted, on a free slot
+    if (!s->ready.empty()) {
+      Slot* free_slot = nullptr;
+      uint32_t busy = 0;
+      for (Slot& sl : s->slots) {
+        if (sl.busy) busy++;
+        else if (!free_slot) free_slot = &sl;
+      }
+      if (free_slot) {
+        Slot& sl = *free_slot;
+        const gmp_status st = launch_ready(s, sl);
+        sl.t_launch = now_ns();
+        if (st != GMP_OK) {
+          for (const Request& rq : s->ready) {
+            complete(s, rq, st, sl.t_launch);
+            if (rq.ws_bytes) s->arena->release(rq.ws_off, rq.ws_bytes);
+            s->in_flight_bytes -= rq.bytes;
+          }
+          s->ready.clear();
+          if (s->error == GMP_OK) s->error = st;
+        } else {
+          sl.reqs = std::move(s->ready);
+          s->ready.clear();
+          sl.busy = true;
+          if (++busy > s->peak_slots) s->peak_slots = busy;
+          s->launches++;
+        }
+        progress = true;
+      }
     }
     if (progress) {
       s->cv.notify_all();
@@ -298,6 +322,7 @@ extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
     if (st != GMP_OK) return st;
     const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
     if (info.raw_len != want) return GMP_ESIZE;
+    if (mode == GMP_MODE_DE && !(info.mode == 1 && info.group % 64 == 0)) return GMP_EINVAL;
     gmpk::DevJob& j = rq.jobs[b];
     j.comp = req->d_stream + o0;
     j.comp_len = o1 - o0;
@@ -353,6 +378,7 @@ extern "C" gmp_status gmp_server_stats(gmp_server* s, gmp_server_info* out) {
   out->in_flight_bytes = s->in_flight_bytes;
   out->peak_in_flight_bytes = s->peak_bytes;
   out->peak_slots = s->peak_slots;
+  out->launches = s->launches;
   out->budget = s->budget;
   return GMP_OK;
 }

@@ -72,7 +72,7 @@ def test_alone_equals_mix(ctx):
     for r in reqs:
         r.reset()
     torch.cuda.synchronize()
-    srv = gmp.Server(ctx, budget_bytes=1 << 30, slots=8)
+    srv = gmp.Server(ctx, budget_bytes=1 << 30, slots=4)
     print(f"[gpu] server mix of {len(reqs)} requests", flush=True)
     for k, r in enumerate(reqs):
         srv.submit(r.d_in, r.stream, r.out, r.status, gmp.MODE_AUTO, tag=k)
@@ -83,7 +83,7 @@ def test_alone_equals_mix(ctx):
     assert sorted(c["tag"] for c in done) == list(range(len(reqs)))
     assert all(c["status"] == 0 for c in done)
     assert all(c["t_submit_ns"] <= c["t_admit_ns"] <= c["t_done_ns"] for c in done)
-    assert info["finished"] == len(reqs) and info["peak_slots"] >= 2
+    assert info["finished"] == len(reqs) and 1 <= info["launches"] <= len(reqs)
     for k, r in enumerate(reqs):
         st, got = r.result()
         assert np.all(st == 0), k
@@ -104,7 +104,7 @@ def test_small_budget_back_pressure(ctx):
             ws += ((8 * i["n_seq"] + i["n_lit"] + 64 + 255) // 256) * 256
         sizes.append(len(r.stream) + len(r.raw) + ws)
     budget = int(max(sizes) * 1.5)
-    srv = gmp.Server(ctx, budget_bytes=budget, workspace_bytes=budget, slots=8)
+    srv = gmp.Server(ctx, budget_bytes=budget, workspace_bytes=budget, slots=4)
     for k, r in enumerate(reqs):
         srv.submit(r.d_in, r.stream, r.out, r.status, gmp.MODE_AUTO, tag=k)
     srv.drain(60000)
