@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Decompressed GB/s of the Gompresso/Bit decoder on one MI355X.
 
-Workload (the plain single-stream configuration): 256 MiB of seeded Zipf text,
-1 MiB blocks each cut into 16 KiB sub-blocks (64 per block), 32 KiB window,
-matches 3..258, code lengths <= 12.  The same data is compressed twice, as an
-ordinary LZ77 stream (resolved by Multi-Round Resolution) and as a
-Dependency-Elimination stream (resolved in one pass).  One step decodes both
-streams, each with one launch of the decoder (one workgroup per block); inputs
-and outputs stay resident in HBM for the whole timed region.
+Headline workload (the plain single-stream configuration; `value`): 256 MiB
+of seeded Zipf text, 1 MiB blocks each cut into 16 KiB sub-blocks (64 per
+block), 32 KiB window, matches 3..258, code lengths <= 12.  The same data is
+compressed twice, as an ordinary LZ77 stream (resolved by Multi-Round
+Resolution) and as a Dependency-Elimination stream (resolved in one pass).
+One step decodes both streams, each with one launch of the decoder (one
+workgroup per block); inputs and outputs stay resident in HBM for the whole
+timed region.
+
+Beside it, on the same GPU and in the same run:
+* batched: 4096 independent blocks of 4 KiB-4 MiB (half text, half CSV-like,
+  ordinary or DE by a coin) in one graph-captured persistent launch, with the
+  sub-block size picked by recompressing a sample and the launch shape by the
+  library's autotuner, against the plain launch of the same blocks;
+* serving: Poisson arrivals of requests of 64 KiB-64 MiB at 10-90 % of the
+  batched peak through the library's request loop (64 GiB budget), with
+  p50/p99 latency and admission wait per load level.
 
 The CPU oracle's compressor generates the compressed inputs and its decoder,
-run block-parallel over the host cores, is the CPU baseline.  Outputs of the
-timed runs are checked byte for byte against the original data.
+run block-parallel over the host cores, is the CPU baseline.  Every decoded
+byte is checked against the original data.
 
 Prints one JSON line (see the field descriptions in the design doc).
 """

@@ -31,7 +31,7 @@ EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_block_info_
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",
            "gmp_batch_destroy", "gmp_batch_graph_create", "gmp_batch_graph_launch", "gmp_autotune",
            "gmp_server_create", "gmp_server_submit", "gmp_server_poll", "gmp_server_drain", "gmp_server_stats",
-           "gmp_server_destroy")
+           "gmp_server_destroy", "gmp_workspace_bytes")
 
 
 class GmpError(RuntimeError):
@@ -99,6 +99,8 @@ def _load():
     L.gmp_server_poll.restype = u32
     L.gmp_server_drain.argtypes = [vp, u32]
     L.gmp_server_stats.argtypes = [vp, C.POINTER(ServerInfo)]
+    L.gmp_workspace_bytes.argtypes = [u32, u32]
+    L.gmp_workspace_bytes.restype = C.c_uint64
     L.gmp_server_destroy.argtypes = [vp]
     L.gmp_server_destroy.restype = None
     for fn in ("gmp_ctx_create", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
@@ -139,6 +141,11 @@ def block_info(h_block) -> dict:
     if st:
         raise GmpError(st, "gmp_block_info_parse")
     return {f: getattr(info, f) for f, _ in BlockInfo._fields_}
+
+
+def workspace_bytes(n_seq: int, n_lit: int) -> int:
+    """Device token workspace one block needs (gmp_workspace_bytes)."""
+    return int(lib.gmp_workspace_bytes(n_seq, n_lit))
 
 
 def stream_info(h_stream) -> tuple[int, int, int]:

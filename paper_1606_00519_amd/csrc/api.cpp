@@ -113,6 +113,10 @@ extern "C" gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_
   return GMP_OK;
 }
 
+extern "C" uint64_t gmp_workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
+  return gmpk::workspace_bytes(n_seq, n_lit);
+}
+
 extern "C" gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks, uint32_t* block_size,
                                       uint64_t* raw_total) {
   if (!h_stream) return GMP_EINVAL;

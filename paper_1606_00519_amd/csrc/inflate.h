@@ -28,9 +28,23 @@ struct DevJob {
 };
 static_assert(sizeof(DevJob) == 80, "DevJob layout");
 
-// workspace bytes for one block
-inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
-  return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256;
+// Token workspace of one block: the final token stream (n_seq 8-byte records,
+// then n_lit literal bytes), then the private areas of the segmented decoder
+// (each decoder lane gets room for twice its share of the block's tokens plus
+// slack; a lane that overflows makes the block fall back to one lane per
+// sub-block, which needs only the final area).
+constexpr uint32_t kPrivSlackRec = 64, kPrivSlackLit = 256;
+__host__ __device__ inline uint64_t final_bytes(uint32_t n_seq, uint32_t n_lit) { return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256; }
+__host__ __device__ inline uint64_t lane_cap_rec(uint32_t n_seq, uint32_t lanes) {
+  return ((2ull * n_seq + lanes - 1) / lanes + kPrivSlackRec + 1) / 2 * 2;  // even: areas stay 16-byte aligned
+}
+__host__ __device__ inline uint64_t lane_cap_lit(uint32_t n_lit, uint32_t lanes) {
+  return (((2ull * n_lit + lanes - 1) / lanes + kPrivSlackLit) + 15) / 16 * 16;
+}
+__host__ __device__ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
+  const uint64_t lanes = 64ull * kMaxDecWaves;
+  return final_bytes(n_seq, n_lit) + lanes * (8 * lane_cap_rec(n_seq, (uint32_t)lanes) + lane_cap_lit(n_lit, (uint32_t)lanes)) +
+         256;
 }
 
 }  // namespace gmpk

@@ -86,7 +86,16 @@ constexpr uint32_t kStageBytes = 32768;       // staging area: bit rings, then t
 constexpr uint32_t kRecRing = 2048;           // staged sequence records (8 bytes each)
 constexpr uint32_t kLitRing = 8192;           // staged literal bytes
 constexpr uint32_t kLitStagedMax = 4096;      // larger literal groups read HBM directly
+constexpr uint32_t kCoopLits = 64;            // longer literal runs are copied by the whole wavefront
+constexpr uint32_t kTightPolls = 64;          // polls of a hand-over counter before pausing between polls
 constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
+constexpr uint32_t kSubMax = 512;             // most sub-blocks of a block decoded in segments
+constexpr uint32_t kOverlapBits = 512;        // bits a segment decoder reads ahead of its start to synchronise
+// Segmented decoding stays off until lanes that do not fall into step within
+// the warm-up are repaired locally: without that, a single such lane sends the
+// whole block back to the one-lane-per-sub-block decoder after the segmented
+// attempt, which costs more than it saves.
+constexpr bool kSegmentedDecode = false;
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
 
 // status codes (same values as the public header)
@@ -174,6 +183,7 @@ struct Misc {
   uint32_t rec_avail, lit_avail;  // fetcher -> resolvers: records / literal bytes staged
   uint32_t g_out[kGRing], g_lit[kGRing];   // fetcher -> resolvers: offsets of staged groups
   uint32_t next_group[kMaxDecWaves];       // resolver -> fetcher: first group it still reads
+  uint32_t coop[kMaxDecWaves][64];         // resolver w: run starts of a cooperative copy pass
   uint32_t done_upto;                      // resolvers: output below this is final
   uint32_t flushed;                        // flusher: output below this is in HBM
   uint32_t next_job;
@@ -181,10 +191,26 @@ struct Misc {
   int err;
 };
 
+// State of the segmented Huffman decoder (A2 when the block qualifies).
+constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8;
+struct Seg {
+  uint32_t sub_start[kSubMax + 1];  // first payload bit of each sub-block; [n_sub] = payload bits
+  uint32_t sub_end[kSubMax];        // bit after each sub-block's end symbol
+  uint32_t cnt_seq[kSubMax], cnt_lit[kSubMax], cnt_raw[kSubMax];  // tokens decoded per sub-block, all lanes
+  uint32_t entry[kMaxLanes], exit_at[kMaxLanes];  // first / past-last symbol boundary each lane decoded
+  uint32_t nrec[kMaxLanes], nlit[kMaxLanes];      // records / literal bytes each lane wrote
+  uint32_t tail[kMaxLanes];                       // literals after a lane's last record, run still open
+  uint32_t flags[kMaxLanes];                      // kSeg* bits
+  uint32_t entry_sub[kMaxLanes];                  // sub-block of the lane's entry
+  uint32_t rec_base[kMaxLanes], lit_base[kMaxLanes], carry[kMaxLanes];
+  uint32_t bad;
+};
+
 // Workgroup-shared memory.
 __shared__ __attribute__((aligned(16))) uint32_t s_big[kRing / 4];     // lookup tables, then the output window
 __shared__ __attribute__((aligned(16))) uint4 s_stage[kStageBytes / 16];  // bit rings, then staged tokens
 __shared__ Misc s_misc;
+__shared__ Seg s_seg;
 
 __device__ __forceinline__ uint8_t* ring_ptr() { return reinterpret_cast<uint8_t*>(s_big); }
 __device__ __forceinline__ uint2* rec_ring() { return reinterpret_cast<uint2*>(s_stage); }
@@ -495,6 +521,212 @@ __device__ int decode_subblock(const SubBlock& sb, uint32_t L, uint32_t lmax, ui
   return kOK;
 }
 
+// ---------------------------------------------------------------- A2 segments
+// Segmented decoding: the block's payload bits are cut into equal segments,
+// one per decoder lane, whatever the sub-block sizes.  A lane whose segment
+// starts inside a sub-block does not know where a symbol starts there, so it
+// starts decoding up to kOverlapBits earlier (or at the sub-block's start)
+// and relies on canonical codes falling back into step within a few symbols
+// (a sub-block start is an exact synchronisation point).  It then decodes,
+// writing its records and literal bytes to a private area, from the first
+// literal/length symbol boundary at or after its segment start (its entry)
+// to the first such boundary at or after the next segment's start (its exit),
+// across sub-block ends.  The block is accepted when every lane's exit is the
+// next lane's entry, no lane failed or overflowed, and the tokens counted
+// per sub-block match the index; the private areas are then packed into the
+// final token stream.  Otherwise the block is decoded again one lane per
+// sub-block.
+struct SegLane {
+  uint32_t p_begin, p_end;      // segment [p_begin, p_end), payload bits
+  uint32_t base_word, n_words;  // the payload words fetched for the lane
+  uint32_t cap_rec, cap_lit;
+  GMEM uint64_t* rec_out;
+  GMEM uint8_t* lit_out;
+};
+
+template <int kDec>
+__device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uint32_t lmax, uint32_t window,
+                               uint32_t max_match) {
+  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  const uint32_t lmask = (1u << lmax) - 1u;
+  const uint32_t nw = g.n_words;
+  const uint32_t* ring_base = reinterpret_cast<const uint32_t*>(s_stage) + 4 * L;
+  uint32_t avail = 0;
+  auto ring_word = [&](uint32_t k) -> uint32_t {
+    if (k < nw && k >= avail) {
+      Spin sp;
+      for (;;) {
+        avail = lds_acquire(&s_misc.avail[L]);
+        if (k < avail) break;
+        if (!sp.pause()) {
+          avail = kDone;
+          break;
+        }
+      }
+    }
+    const uint32_t w = ring_base[((k >> 2) & (kRows - 1)) * (4 * kLanes) + (k & 3)];
+    return k < nw ? w : 0u;
+  };
+  uint32_t w0, w1, w2, w3, nx, rd, sbit;
+  // window at absolute payload bit p (p >= 32 * base_word, never moving back)
+  auto load = [&](uint32_t p) {
+    const uint32_t k = p / 32 - g.base_word;
+    w0 = ring_word(k);
+    w1 = ring_word(k + 1);
+    w2 = ring_word(k + 2);
+    w3 = ring_word(k + 3);
+    nx = ring_word(k + 4);
+    rd = k + 4;
+    sbit = p & 31;
+    s_misc.rd[L] = k;
+  };
+  // the symbol at the window under `state`: n bits in all (0: no such code)
+  auto peek = [&](uint32_t state, uint32_t& n, uint32_t& kind, uint32_t& val) {
+    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, sbit), hi = __builtin_amdgcn_alignbit(w2, w1, sbit);
+    const uint32_t e = s_big[(state << kLutBits) | (lo & lmask)];
+    n = e & 31u;
+    const uint32_t x = (e >> 5) & 15u;
+    kind = (e >> 9) & 3u;
+    val = (e >> 16) + __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi, lo, n), 0, x);
+    n += x;
+  };
+  // move the window on by b (< 32) bits
+  auto advance = [&](uint32_t b) {
+    sbit += b;
+    const bool sh = sbit >= 32;
+    sbit &= 31;
+    w0 = sh ? w1 : w0;
+    w1 = sh ? w2 : w1;
+    w2 = sh ? w3 : w2;
+    w3 = sh ? nx : w3;
+    rd += sh ? 1u : 0u;
+    nx = ring_word(rd);
+    s_misc.rd[L] = rd - 4;
+  };
+  // the sub-block holding p_begin
+  uint32_t lo_s = 0, hi_s = n_sub - 1;
+  while (lo_s < hi_s) {
+    const uint32_t mid = (lo_s + hi_s + 1) / 2;
+    if (s_seg.sub_start[mid] <= g.p_begin) lo_s = mid;
+    else hi_s = mid - 1;
+  }
+  uint32_t sb = lo_s;
+  uint32_t pos = g.p_begin >= s_seg.sub_start[sb] + kOverlapBits ? g.p_begin - kOverlapBits : s_seg.sub_start[sb];
+  uint32_t sub_end = s_seg.sub_end[sb];
+  uint32_t state = 0, n, kind, val;
+  load(pos);
+  // warm-up: decode without output up to the entry.  The window only ever
+  // moves a little at a time (never further than the lane's bit ring holds):
+  // an invalid code or an end symbol that does not end the sub-block means
+  // the decoder is out of step, and it moves on by one bit.
+  for (;;) {
+    if (state == 0 && pos >= g.p_begin) break;
+    if (pos >= sub_end) {
+      // the sub-block's end (or past it, out of step): resume at the next
+      // sub-block's start, an exact symbol boundary at most 127 bits on
+      sb++;
+      pos = s_seg.sub_start[sb];
+      state = 0;
+      if (sb >= n_sub) break;
+      sub_end = s_seg.sub_end[sb];
+      load(pos);
+      continue;
+    }
+    peek(state, n, kind, val);
+    if (n == 0 || (state == 0 && kind == kKindEnd && pos + n != sub_end)) {
+      advance(1);
+      pos += 1;
+      state = 0;
+      continue;
+    }
+    advance(n);
+    pos += n;
+    state = (state == 0 && kind == kKindLen) ? 1u : 0u;
+  }
+  const uint32_t entry = pos, entry_sub = sb;
+  uint32_t flags = (sb < n_sub && pos != s_seg.sub_start[sb]) ? kSegMid : 0u;
+  bool first_piece = (flags & kSegMid) != 0;
+  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0;
+  bool any_eob = false, fail = false;
+  if (sb < n_sub && pos < g.p_end) {
+    for (;;) {
+      bool is_end = false;
+      for (;;) {
+        peek(state, n, kind, val);
+        advance(n);
+        pos += n;
+        const bool is_dist = state != 0;
+        const bool is_lit = !is_dist && kind == kKindLit;
+        const bool is_len = !is_dist && kind == kKindLen;
+        is_end = !is_dist && kind == kKindEnd;
+        bool bad = n == 0 || pos > sub_end;
+        bad = bad || (is_dist && (plen > max_match || val > window || sc >= g.cap_rec)) || (is_lit && lc >= g.cap_lit);
+        if (is_dist && !bad) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+        if (is_lit && !bad) g.lit_out[lc] = (uint8_t)val;
+        sc += is_dist ? 1u : 0u;
+        lc += is_lit ? 1u : 0u;
+        pseq += is_dist ? 1u : 0u;
+        plit += is_lit ? 1u : 0u;
+        praw += is_dist ? plen : (is_lit ? 1u : 0u);
+        run = is_dist ? 0u : run + (is_lit ? 1u : 0u);
+        plen = is_len ? val : plen;
+        state = is_len ? 1u : 0u;
+        if (bad) {
+          fail = true;
+          break;
+        }
+        if (is_end || (state == 0 && pos >= g.p_end)) break;
+      }
+      if (fail) break;
+      if (!is_end) break;  // reached the segment's end inside sub-block sb
+      // sub-block sb ends here: its end symbol must end exactly at its length
+      if (pos != sub_end) {
+        fail = true;
+        break;
+      }
+      if (run || (first_piece && sc == 0)) {
+        // the literal run the end closes is a sequence without a match; with
+        // no literals of its own, a lane's first such sequence only exists if
+        // the previous lanes' trailing literals flow into it (decided later)
+        if (sc >= g.cap_rec) {
+          fail = true;
+          break;
+        }
+        g.rec_out[sc] = (uint64_t)run;
+        if (run) pseq++;
+        else flags |= kSegMaybe;
+        sc++;
+      }
+      any_eob = true;
+      atomicAdd(&s_seg.cnt_seq[sb], pseq);
+      atomicAdd(&s_seg.cnt_lit[sb], plit);
+      atomicAdd(&s_seg.cnt_raw[sb], praw);
+      pseq = plit = praw = run = 0;
+      first_piece = false;
+      sb++;
+      pos = s_seg.sub_start[sb];
+      state = 0;
+      if (sb >= n_sub || pos >= g.p_end) break;
+      sub_end = s_seg.sub_end[sb];
+      load(pos);
+    }
+    if (!fail && sb < n_sub && (pseq | plit | praw)) {
+      atomicAdd(&s_seg.cnt_seq[sb], pseq);
+      atomicAdd(&s_seg.cnt_lit[sb], plit);
+      atomicAdd(&s_seg.cnt_raw[sb], praw);
+    }
+  }
+  if (fail) flags |= kSegFail;
+  if (sc == 0 && !any_eob) flags |= kSegPass;
+  s_seg.entry[L] = entry;
+  s_seg.exit_at[L] = fail ? kDone : pos;
+  s_seg.nrec[L] = sc;
+  s_seg.nlit[L] = lc;
+  s_seg.tail[L] = run;
+  s_seg.flags[L] = flags;
+  s_seg.entry_sub[L] = entry_sub;
+}
+
 // ---------------------------------------------------------------- ring helpers
 __device__ __forceinline__ uint4 ring_read16(const uint8_t* ring, uint32_t p) {
   const uint32_t a = p & kRingMask;
@@ -556,19 +788,47 @@ __device__ __forceinline__ void ring_write(uint8_t* ring, uint32_t p, uint4 v, u
 // (dist < len) repeats them with period dist.
 __device__ __forceinline__ void copy_match(uint8_t* ring, uint32_t dst, uint32_t len, uint32_t dist) {
   const uint32_t src = dst - dist;
-  if (dist >= len || dist >= 16) {
-    // each 16-byte source chunk ends at or before its destination chunk
-    for (uint32_t k = 0; k < len; k += 16) ring_write(ring, dst + k, ring_read16(ring, src + k), min(16u, len - k));
+  if (dist < 16 && dist < len) {
+    // short period: the first 16 output bytes are built in registers from the
+    // dist bytes before dst (one read), then written every p16 = dist *
+    // floor(16 / dist) bytes, a whole number of periods
+    const uint4 q = ring_read16(ring, src);
+    uint64_t lo = (uint64_t)q.x | ((uint64_t)q.y << 32), hi = (uint64_t)q.z | ((uint64_t)q.w << 32);
+    if (dist < 8) {
+      lo &= (1ull << (8 * dist)) - 1ull;
+      hi = 0;
+    } else {
+      hi &= (1ull << (8 * (dist - 8))) - 1ull;
+    }
+    for (uint32_t l = dist; l < 16; l *= 2) {  // append the pattern to itself
+      const uint32_t sh = 8 * l;
+      if (sh >= 64) {
+        hi |= lo << (sh - 64);
+      } else {
+        hi |= (hi << sh) | (lo >> (64 - sh));
+        lo |= lo << sh;
+      }
+    }
+    const uint4 v = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    const uint32_t p16 = dist * (16u / dist);
+    for (uint32_t k = 0; k < len; k += p16) ring_write(ring, dst + k, v, min(16u, len - k));
     return;
   }
-  // dist < 16 and overlapping: the first min(len, 16) bytes one at a time,
-  // then whole periods: the output repeats with period p16 = dist * (16 / dist).
-  const uint32_t head = min(len, 16u);
-  for (uint32_t k = 0; k < head; k++) ring[(dst + k) & kRingMask] = ring[(src + k) & kRingMask];
-  if (len <= 16) return;
-  const uint32_t p16 = dist * (16u / dist);
-  const uint4 v = ring_read16(ring, dst);
-  for (uint32_t k = p16; k < len; k += p16) ring_write(ring, dst + k, v, min(16u, len - k));
+  if (dist >= len || dist >= 64) {
+    // no chunk of a batch of four reads bytes the batch writes: reads first
+    for (uint32_t k = 0; k < len; k += 64) {
+      uint4 c[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (k + 16 * j < len) c[j] = ring_read16(ring, src + k + 16 * j);
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (k + 16 * j < len) ring_write(ring, dst + k + 16 * j, c[j], min(16u, len - k - 16 * j));
+    }
+    return;
+  }
+  // 16 <= dist < 64, overlapping: each 16-byte chunk ends at or before its destination
+  for (uint32_t k = 0; k < len; k += 16) ring_write(ring, dst + k, ring_read16(ring, src + k), min(16u, len - k));
 }
 
 __device__ __forceinline__ uint4 lit_read16(uint32_t p) {
@@ -639,6 +899,40 @@ __device__ __noinline__ void copy_lits_hbm(const GMEM uint8_t* src, uint32_t pos
 __device__ __noinline__ void stream_lits_hbm(const GMEM uint8_t* src, uint32_t base, uint32_t n, uint32_t lane) {
   uint8_t* ring = ring_ptr();
   for (uint32_t k = lane * 16; k < n; k += 1024) ring_write(ring, base + k, gload16(src + k), min(16u, n - k));
+}
+
+// Cooperative literal copy: lane i's run of n bytes goes from literal-ring
+// position lsrc to window position pos.  The runs are cut into 16-byte units
+// and the units of all runs are spread over the lanes, 64 per pass, so a
+// long run costs its length / 1 KiB passes instead of length / 16 steps of
+// one lane.  A unit's owner is found from the run starts marked in a
+// 64-entry scratch row and a prefix maximum.
+__device__ __forceinline__ uint32_t shfl(uint32_t v, uint32_t src_lane) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane << 2), (int)v);
+}
+__device__ void coop_lits(uint32_t pos, uint32_t lsrc, uint32_t n, uint32_t* scratch) {
+  uint8_t* ring = ring_ptr();
+  const uint32_t lane = lane_id();
+  const uint32_t units = (n + 15) >> 4;
+  const uint32_t inc = wave_incl_scan(units);
+  const uint32_t first = inc - units, total = readlane(inc, 63);
+  uint32_t owner_carry = 0;
+  for (uint32_t b = 0; b < total; b += 64) {
+    scratch[lane] = 0;
+    if (units && first >= b && first < b + 64) scratch[first - b] = lane + 1;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t mark = wave_incl_max(scratch[lane]);
+    const uint32_t owner = mark ? mark - 1 : owner_carry;
+    owner_carry = readlane(owner, 63);
+    const uint32_t o_first = shfl(first, owner), o_src = shfl(lsrc, owner), o_pos = shfl(pos, owner),
+                   o_n = shfl(n, owner);
+    const uint32_t u = b + lane;
+    if (u < total) {
+      const uint32_t off = (u - o_first) << 4;
+      ring_write(ring, o_pos + off, lit_read16(o_src + off), min(16u, o_n - off));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // ---------------------------------------------------------------- A3-A6
@@ -732,20 +1026,22 @@ __device__ void fetch_tokens(const LzArgs& a) {
 // false if the wait was abandoned.
 __device__ __forceinline__ bool wait_window(uint32_t end) {
   Spin sp;
-  for (;;) {
+  for (uint32_t i = 0;; i++) {
     const uint32_t done = lds_acquire(&s_misc.done_upto), fl = lds_acquire(&s_misc.flushed);
     const uint32_t low = min(done > 32768u ? done - 32768u : 0u, fl);
     if (end <= low + kRing) return true;
-    if (!sp.pause()) return false;
+    if (i >= kTightPolls && !sp.pause()) return false;
   }
 }
-// Wait until *p >= v; false if the wait was abandoned.
+// Wait until *p >= v; false if the wait was abandoned.  The first polls are
+// back to back: hand-overs between resolver wavefronts are on the critical
+// path and usually arrive within a few hundred cycles.
 __device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t v, uint32_t& seen) {
   Spin sp;
-  for (;;) {
+  for (uint32_t i = 0;; i++) {
     seen = lds_acquire(p);
     if (seen >= v) return true;
-    if (!sp.pause()) return false;
+    if (i >= kTightPolls && !sp.pause()) return false;
   }
 }
 __device__ __forceinline__ bool wait_done(uint32_t pos) {
@@ -770,15 +1066,20 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
     const uint2 rec = valid ? rec_ring()[j % kRecRing] : make_uint2(0u, 0u);
     const uint32_t g_out = s_misc.g_out[g % kGRing], g_lit = s_misc.g_lit[g % kGRing];
     uint32_t L = rec.x;
-    const uint32_t M = rec.y & 0xFFFFu;
+    const uint32_t M0 = rec.y & 0xFFFFu;
     const uint32_t D = rec.y >> 16;
     // A3: two exclusive prefix sums over the group's sequences
     const uint32_t inc_lit = wave_incl_scan(L);
-    const uint32_t inc_out = wave_incl_scan(L + M);
+    const uint32_t inc_out = wave_incl_scan(L + M0);
     const uint32_t tot_lit = readlane(inc_lit, 63);
     uint32_t lsrc = g_lit + inc_lit - L;
-    uint32_t pos = g_out + inc_out - (L + M);
-    const uint32_t end = pos + L + M;
+    uint32_t pos = g_out + inc_out - (L + M0);
+    const uint32_t end = pos + L + M0;
+    // a distance reaching before the block's start is an error (EDIST); such
+    // a copy is dropped so that resolution still ends
+    const bool bad_dist = valid && M0 > 0 && D > pos + L;
+    if (__ballot(bad_dist)) set_err(kEDIST);
+    const uint32_t M = bad_dist ? 0u : M0;
     const uint32_t m_cnt = min(64u, a.n_seq - g0);
     const uint32_t g_end = g_out + readlane(inc_out, 63);
     // literals come from the LDS ring unless the group holds more than half of it
@@ -788,26 +1089,36 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       break;
     uint32_t rounds = 0;
     bool split = false;
-    // fast path: no copy of the group wraps around the window or the literal
-    // ring, none overlaps its own output, and the group fits the window
+    // fast path: the group's literals are staged and its output fits the
+    // window; "plain" when moreover no copy wraps around the ring or the
+    // literal ring and none overlaps its own output (most groups)
+    const bool fast = lits_staged && g_end - g_out <= kSpanCap;
     const uint32_t src0 = pos + L - D;
-    const bool lane_ok =
-        !valid || ((pos & kRingMask) + L + M <= kRing &&
-                   (M == 0 || (D >= M && (src0 & kRingMask) + ((M + 15) & ~15u) <= kRing)) &&
+    const bool lane_plain =
+        !valid || ((pos & kRingMask) + L + M0 <= kRing &&
+                   (M0 == 0 || (D >= M0 && (src0 & kRingMask) + ((M0 + 15) & ~15u) <= kRing)) &&
                    (L == 0 || (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing));
-    const bool fast = lits_staged && g_end - g_out <= kSpanCap && !__ballot(!lane_ok);
+    const bool plain = !__ballot(!lane_plain);
     if (fast) {
       if (!wait_window(g_end)) break;
-      // A4: literal strings into the window, ahead of earlier groups
-      if (valid && L) {
-        uint8_t* d = ring + (pos & kRingMask);
-        const uint8_t* q = lit_ring() + (lsrc & (kLitRing - 1));
-        for (uint32_t k = 0; k < L; k += 16) write_upto16(d + k, read16(q + k), min(16u, L - k));
+      // A4: literal strings into the window, ahead of earlier groups; long
+      // runs are spread over the whole wavefront
+      const uint32_t max_l = readlane(wave_incl_max(valid ? L : 0u), 63);
+      if (max_l > kCoopLits) {
+        coop_lits(pos, lsrc, valid ? L : 0u, s_misc.coop[w]);
+      } else if (plain) {
+        if (valid && L) {
+          uint8_t* d = ring + (pos & kRingMask);
+          const uint8_t* q = lit_ring() + (lsrc & (kLitRing - 1));
+          for (uint32_t k = 0; k < L; k += 16) write_upto16(d + k, read16(q + k), min(16u, L - k));
+        }
+      } else if (valid && L) {
+        for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
       }
       lds_release(&s_misc.next_group[w], g + kRes);
       const uint32_t dst = pos + L;
       const bool has = valid && M > 0;
-      const uint32_t need_end = src0 + M;  // no overlap on this path: the source is [src0, src0 + M)
+      const uint32_t need_end = dst - D + min(M, D);  // bytes a copy reads that it does not write
       // Round membership depends only on positions.  A6 (DE): every
       // back-reference of the group in the one pass.  A5 (MRR): round r takes
       // the pending lanes whose source ends at or below the destination of the
@@ -834,8 +1145,14 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // before the groups in front of it have finished.
       const uint32_t need = min(readlane(wave_incl_max(has ? need_end : 0u), 63), g_out);
       if (!wait_done(need)) break;
-      for (uint32_t r = 1; r <= rounds; r++) {
-        if (my_round == r) copy_nowrap(ring, dst, src0, M);
+      if (plain) {
+        for (uint32_t r = 1; r <= rounds; r++) {
+          if (my_round == r) copy_nowrap(ring, dst, src0, M);
+        }
+      } else {
+        for (uint32_t r = 1; r <= rounds; r++) {
+          if (my_round == r) copy_match(ring, dst, M, D);
+        }
       }
       // its output is final once everything in front of it is
       if (!wait_done(g_out)) break;
@@ -947,6 +1264,157 @@ __device__ void flush_output(const LzArgs& a) {
   }
 }
 
+// ---------------------------------------------------------------- A0/A2 segmented
+// The segmented form of A2 for a block that qualifies: its index is
+// consistent, it has at most kSubMax sub-blocks, its payload gives every lane
+// at least two 16-byte rows, and its workspace holds the private areas.
+// Returns true when the block's final token stream is in the workspace;
+// false leaves the block to the one-lane-per-sub-block decoder (which also
+// reports any error).  Called by every thread of the workgroup.
+template <int kDec>
+__device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, const GMEM uint8_t* payload_bytes,
+                                 uint32_t n_sub, uint32_t n_seq, uint32_t n_lit, uint32_t payload, uint32_t lmax,
+                                 uint32_t window, uint32_t max_match, GMEM uint64_t* ws_seq, GMEM uint8_t* ws_lit) {
+  constexpr uint32_t kThreads = 64 * (kDec + 2), kLanes = 64 * kDec;
+  Misc& sh = s_misc;
+  const uint32_t t = threadIdx.x, wave = t >> 6;
+  const uint32_t pw = payload / 4;  // payload words (a multiple of 4)
+  const uint64_t fin = final_bytes(n_seq, n_lit);
+  const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, kLanes);
+  const uint64_t lane_bytes = 8 * cap_rec + cap_lit;
+  if (!kSegmentedDecode || n_sub == 0 || n_sub > kSubMax || pw < 8 * kLanes || payload >= (1u << 28) ||
+      job.ws_len < fin + kLanes * lane_bytes)
+    return false;
+  // sub-block table from the index
+  if (t == 0) s_seg.bad = 0;
+  uint32_t carry[4] = {0, 0, 0, 0};
+  for (uint32_t c = 0; c < n_sub; c += kThreads) {
+    const uint32_t s = c + t;
+    uint32_t bit_len = 0, sseq = 0, slit = 0, sraw = 0;
+    if (s < n_sub) {
+      const uint4 e = gload16(idx + kIdxBytes * s);
+      bit_len = e.x;
+      sseq = e.y;
+      slit = e.z;
+      sraw = e.w;
+    }
+    const uint32_t nwords = (uint32_t)((((uint64_t)bit_len + 127) >> 7) << 2);
+    uint32_t v[4] = {nwords, sseq, slit, sraw}, tot[4];
+    block_excl_scan4<kThreads>(v, tot);
+    const uint32_t word_off = carry[0] + v[0];
+    if (s < n_sub) {
+      if (bit_len == 0 || (uint64_t)word_off + nwords > pw) s_seg.bad = 1;
+      s_seg.sub_start[s] = 32 * word_off;
+      s_seg.sub_end[s] = 32 * word_off + bit_len;
+      s_seg.cnt_seq[s] = 0;
+      s_seg.cnt_lit[s] = 0;
+      s_seg.cnt_raw[s] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) carry[i] += tot[i];
+  }
+  if (t == 0) {
+    s_seg.sub_start[n_sub] = 32 * pw;
+    if (carry[0] != pw || carry[1] != n_seq || carry[2] != n_lit) s_seg.bad = 1;
+  }
+  __syncthreads();
+  if (s_seg.bad) return false;
+  // segments: equal runs of 16-byte rows; each lane fetches from where its
+  // warm-up may start to a little past its segment's end
+  GMEM uint8_t* priv = gmem(job.ws) + fin;
+  SegLane g;
+  if (t < kLanes) {
+    const uint32_t rows = pw / 4;
+    const uint32_t r0 = (uint32_t)((uint64_t)rows * t / kLanes), r1 = (uint32_t)((uint64_t)rows * (t + 1) / kLanes);
+    g.p_begin = 128 * r0;
+    g.p_end = 128 * r1;
+    const uint32_t warm = g.p_begin > kOverlapBits ? g.p_begin - kOverlapBits : 0u;
+    g.base_word = (warm / 32) & ~3u;
+    g.n_words = min(pw, 4 * r1 + 8) - g.base_word;
+    g.cap_rec = (uint32_t)cap_rec;
+    g.cap_lit = (uint32_t)cap_lit;
+    g.rec_out = (GMEM uint64_t*)(priv + lane_bytes * t);
+    g.lit_out = priv + lane_bytes * t + 8 * cap_rec;
+    sh.sub_woff[t] = g.base_word;
+    sh.sub_nw[t] = g.n_words;
+    sh.rd[t] = 0;
+    sh.avail[t] = 0;
+  }
+  __syncthreads();
+  if (wave == kDec) {
+    fetch_bitstreams<kDec>(payload_bytes);
+  } else if (t < kLanes) {
+    decode_segment<kDec>(g, t, n_sub, lmax, window, max_match);
+    lds_release(&sh.rd[t], kDone);
+  }
+  __syncthreads();
+  // consistency: lanes meet, runs of literals carried across lane boundaries
+  uint32_t skip = 0, carry_in = 0, flags = 0;
+  if (t < kLanes) {
+    flags = s_seg.flags[t];
+    bool ok = !(flags & kSegFail) && s_seg.entry[t] == (t ? s_seg.exit_at[t - 1] : 0u) &&
+              (t + 1 < kLanes || s_seg.exit_at[t] == 32 * pw);
+    if (flags & kSegMid) {
+      for (uint32_t j = t; j-- > 0;) {
+        carry_in += s_seg.tail[j];
+        if (!(s_seg.flags[j] & kSegPass)) break;
+      }
+    } else if (t && s_seg.tail[t - 1]) {
+      ok = false;  // an open literal run must continue in the next lane
+    }
+    if ((flags & kSegMaybe) && carry_in) atomicAdd(&s_seg.cnt_seq[s_seg.entry_sub[t]], 1u);
+    skip = (flags & kSegMaybe) && !carry_in ? 1u : 0u;
+    if (!ok) s_seg.bad = 1;
+  }
+  __syncthreads();
+  for (uint32_t s = t; s < n_sub; s += kThreads) {
+    const uint4 e = gload16(idx + kIdxBytes * s);
+    if (s_seg.cnt_seq[s] != e.y || s_seg.cnt_lit[s] != e.z || s_seg.cnt_raw[s] != e.w) s_seg.bad = 1;
+  }
+  __syncthreads();
+  if (s_seg.bad) return false;
+  // pack the private areas into the final token stream
+  uint32_t v[4] = {0, 0, 0, 0}, tot[4];
+  if (t < kLanes) {
+    v[0] = s_seg.nrec[t] - skip;
+    v[1] = s_seg.nlit[t];
+  }
+  block_excl_scan4<kThreads>(v, tot);
+  if (tot[0] != n_seq || tot[1] != n_lit) return false;  // cannot happen once the counts matched
+  if (t < kLanes) {
+    const uint32_t nrec = s_seg.nrec[t], nlit = s_seg.nlit[t];
+    const GMEM uint64_t* rs = g.rec_out;
+    GMEM uint64_t* rd = ws_seq + v[0] - skip;
+    for (uint32_t i = skip; i < nrec; i += 16) {
+      uint64_t r[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) r[j] = i + j < nrec ? rs[i + j] : 0ull;
+      if (i == skip) r[0] += carry_in;  // literals of earlier lanes that open this lane's first sequence
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if (i + j < nrec) rd[i + j] = r[j];
+    }
+    const GMEM uint8_t* ls = g.lit_out;
+    GMEM uint8_t* ld = ws_lit + v[1];
+    for (uint32_t i = 0; i < nlit; i += 64) {
+      uint4 q[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) q[j] = i + 16 * j < nlit ? gload16(ls + i + 16 * j) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint32_t k = i + 16 * j;
+        if (k + 16 <= nlit) {
+          gstore16(ld + k, q[j]);
+        } else if (k < nlit) {
+          const uint32_t w[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+          for (uint32_t b = 0; k + b < nlit; b++) ld[k + b] = (uint8_t)(w[b / 4] >> (8 * (b % 4)));
+        }
+      }
+    }
+  }
+  return true;
+}
+
 // ---------------------------------------------------------------- kernel
 __device__ __forceinline__ uint32_t ld32(const GMEM uint8_t* p) { return gload32(p); }
 
@@ -1033,8 +1501,10 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   const GMEM uint8_t* payload_bytes = blk + kHdrBytes + kIdxBytes * n_sub + 16;
   GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
   GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
+  const bool segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
+                                                max_match, ws_seq, ws_lit);
   uint32_t carry[4] = {0, 0, 0, 0};
-  for (uint32_t c = 0; c < n_sub; c += kLanes) {
+  for (uint32_t c = 0; !segmented && c < n_sub; c += kLanes) {
     const uint32_t s = c + t;
     const bool mine = t < kLanes && s < n_sub;
     uint32_t bit_len = 0, sseq = 0, slit = 0, sraw = 0;
@@ -1083,7 +1553,8 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
     __syncthreads();
   }
   // the index must account for the whole payload and the header counts
-  if (t == 0 && (carry[0] * 4ull != payload || carry[1] != n_seq || carry[2] != n_lit || carry[3] != raw_len))
+  if (!segmented && t == 0 &&
+      (carry[0] * 4ull != payload || carry[1] != n_seq || carry[2] != n_lit || carry[3] != raw_len))
     set_err(kEFORMAT);
   __syncthreads();  // workspace writes of all lanes are visible after this barrier
   if (sh.err || sh.abort) {
@@ -1119,7 +1590,7 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   }
   __syncthreads();
   stamp(job, 3);
-  if (t == 0) *status = sh.abort ? kESTALL : kOK;
+  if (t == 0) *status = sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
 }
 
 template <int kDec, int kMode>

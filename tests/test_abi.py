@@ -58,3 +58,10 @@ def test_stream_info_long_block_table(hip_lib_built):
     data = synth.csv_rows(3 << 20).tobytes()
     s = oracle.compress(data, oracle.CompressParams(block_size=4096, sub_target_raw=1024))
     assert gmp.stream_info(s) == (768, 4096, len(data))
+
+
+def test_workspace_bytes_covers_token_stream(hip_lib_built):
+    import paper_1606_00519_amd as gmp
+    for n_seq, n_lit in ((0, 0), (1, 0), (130000, 260000), (5, 1 << 20)):
+        ws = gmp.workspace_bytes(n_seq, n_lit)
+        assert ws >= 8 * n_seq + n_lit + 64 and ws % 256 == 0
