@@ -129,9 +129,9 @@ gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_block_info*
 /* Device token workspace one block needs, from its header's n_seq and n_lit: the
  * token stream between the Huffman and the LZ77 stages (section "Gompresso
  * Overview": sequences and literal strings) plus the segmented decoder's
- * per-lane areas.  Contexts, batches and servers allocate it themselves; a
+ * per-lane areas, which depend on the block's compressed bytes (comp_len).  Contexts, batches and servers allocate it themselves; a
  * server's budget counts it per request. */
-uint64_t gmp_workspace_bytes(uint32_t n_seq, uint32_t n_lit);
+uint64_t gmp_workspace_bytes(uint32_t n_seq, uint32_t n_lit, uint64_t comp_len);
 /* Stream header: number of blocks, block size and total raw bytes. */
 gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks, uint32_t* block_size,
                            uint64_t* raw_total);

@@ -99,7 +99,7 @@ def _load():
     L.gmp_server_poll.restype = u32
     L.gmp_server_drain.argtypes = [vp, u32]
     L.gmp_server_stats.argtypes = [vp, C.POINTER(ServerInfo)]
-    L.gmp_workspace_bytes.argtypes = [u32, u32]
+    L.gmp_workspace_bytes.argtypes = [u32, u32, C.c_uint64]
     L.gmp_workspace_bytes.restype = C.c_uint64
     L.gmp_server_destroy.argtypes = [vp]
     L.gmp_server_destroy.restype = None
@@ -143,9 +143,9 @@ def block_info(h_block) -> dict:
     return {f: getattr(info, f) for f, _ in BlockInfo._fields_}
 
 
-def workspace_bytes(n_seq: int, n_lit: int) -> int:
+def workspace_bytes(n_seq: int, n_lit: int, comp_len: int) -> int:
     """Device token workspace one block needs (gmp_workspace_bytes)."""
-    return int(lib.gmp_workspace_bytes(n_seq, n_lit))
+    return int(lib.gmp_workspace_bytes(n_seq, n_lit, comp_len))
 
 
 def stream_info(h_stream) -> tuple[int, int, int]:

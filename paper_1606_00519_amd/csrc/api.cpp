@@ -113,8 +113,8 @@ extern "C" gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_
   return GMP_OK;
 }
 
-extern "C" uint64_t gmp_workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
-  return gmpk::workspace_bytes(n_seq, n_lit);
+extern "C" uint64_t gmp_workspace_bytes(uint32_t n_seq, uint32_t n_lit, uint64_t comp_len) {
+  return gmpk::workspace_bytes(n_seq, n_lit, comp_len);
 }
 
 extern "C" gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks, uint32_t* block_size,
@@ -219,7 +219,7 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
   if (out_len != info.raw_len) return GMP_ESIZE;
   if (!d_out && out_len) return GMP_EINVAL;
   HIP_OK(hipSetDevice(c->device));
-  const size_t ws = gmpk::workspace_bytes(info.n_seq, info.n_lit);
+  const size_t ws = gmpk::workspace_bytes(info.n_seq, info.n_lit, block_len);
   if ((st = ctx_reserve(c, 1, ws)) != GMP_OK) return st;
   gmpk::DevJob& j = c->h_jobs[0];
   j.comp = d_block;
@@ -258,7 +258,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     if (infos[b].block_bytes > offs[b + 1] - offs[b]) return GMP_EFORMAT;
     const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
     if (infos[b].raw_len != want) return GMP_ESIZE;
-    ws_total += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
+    ws_total += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit, offs[b + 1] - offs[b]);
   }
   HIP_OK(hipSetDevice(c->device));
   if ((st = ctx_reserve(c, nb, ws_total)) != GMP_OK) return st;
@@ -270,7 +270,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     j.out = d_out + (uint64_t)b * bs;
     j.out_len = infos[b].raw_len;
     j.ws = c->d_ws + ws_off;
-    j.ws_len = gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit);
+    j.ws_len = gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit, j.comp_len);
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = d_status + b;
@@ -291,7 +291,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
   for (uint32_t i = 0; i < n_jobs; i++) {
     const gmp_job& j = h_jobs[i];
     if (!j.d_comp || (reinterpret_cast<uintptr_t>(j.d_comp) & 3) || (!j.d_out && j.out_len)) return GMP_EINVAL;
-    ws_total += gmpk::workspace_bytes(j.n_seq, j.n_lit);
+    ws_total += gmpk::workspace_bytes(j.n_seq, j.n_lit, j.comp_len);
   }
   gmp_batch* b = new (std::nothrow) gmp_batch();
   if (!b) return GMP_ENOMEM;
@@ -319,7 +319,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     d.out = j.d_out;
     d.out_len = j.out_len;
     d.ws = b->d_ws + ws_off;
-    d.ws_len = gmpk::workspace_bytes(j.n_seq, j.n_lit);
+    d.ws_len = gmpk::workspace_bytes(j.n_seq, j.n_lit, j.comp_len);
     d.rounds = j.d_rounds;
     d.times = j.d_times;
     d.status = d_status + i;

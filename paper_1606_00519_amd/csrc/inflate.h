@@ -34,17 +34,26 @@ static_assert(sizeof(DevJob) == 80, "DevJob layout");
 // slack; a lane that overflows makes the block fall back to one lane per
 // sub-block, which needs only the final area).
 constexpr uint32_t kPrivSlackRec = 64, kPrivSlackLit = 256;
+// per-lane extras of the segmented decoder: a log of its first symbol
+// boundaries, and room for the tokens of a repair of its start
+constexpr uint32_t kLogN = 128, kRepRec = 128, kRepLit = 512;
+constexpr uint32_t kLaneExtra = 4 * kLogN + 8 * kRepRec + kRepLit;
 __host__ __device__ inline uint64_t final_bytes(uint32_t n_seq, uint32_t n_lit) { return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256; }
 __host__ __device__ inline uint64_t lane_cap_rec(uint32_t n_seq, uint32_t lanes) {
   return ((2ull * n_seq + lanes - 1) / lanes + kPrivSlackRec + 1) / 2 * 2;  // even: areas stay 16-byte aligned
 }
-__host__ __device__ inline uint64_t lane_cap_lit(uint32_t n_lit, uint32_t lanes) {
-  return (((2ull * n_lit + lanes - 1) / lanes + kPrivSlackLit) + 15) / 16 * 16;
+__host__ __device__ inline uint64_t lane_cap_lit(uint32_t n_lit, uint64_t comp_len, uint32_t lanes) {
+  // a lane's share of the compressed bits, at two bits or more per literal
+  // (literal-heavy stretches, such as a block's start, hold far more than
+  // the block's average), never more than the block's literals
+  const uint64_t by_bits = (4 * comp_len + lanes - 1) / lanes + kPrivSlackLit;
+  const uint64_t c = by_bits < (uint64_t)n_lit + kPrivSlackLit ? by_bits : (uint64_t)n_lit + kPrivSlackLit;
+  return (c + 15) / 16 * 16;
 }
-__host__ __device__ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit) {
-  const uint64_t lanes = 64ull * kMaxDecWaves;
-  return final_bytes(n_seq, n_lit) + lanes * (8 * lane_cap_rec(n_seq, (uint32_t)lanes) + lane_cap_lit(n_lit, (uint32_t)lanes)) +
-         256;
+__host__ __device__ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_lit, uint64_t comp_len) {
+  const uint32_t lanes = 64 * kMaxDecWaves;
+  return final_bytes(n_seq, n_lit) +
+         (uint64_t)lanes * (8 * lane_cap_rec(n_seq, lanes) + lane_cap_lit(n_lit, comp_len, lanes) + kLaneExtra) + 256;
 }
 
 }  // namespace gmpk

@@ -90,12 +90,9 @@ constexpr uint32_t kCoopLits = 64;            // longer literal runs are copied 
 constexpr uint32_t kTightPolls = 64;          // polls of a hand-over counter before pausing between polls
 constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
 constexpr uint32_t kSubMax = 512;             // most sub-blocks of a block decoded in segments
-constexpr uint32_t kOverlapBits = 512;        // bits a segment decoder reads ahead of its start to synchronise
-// Segmented decoding stays off until lanes that do not fall into step within
-// the warm-up are repaired locally: without that, a single such lane sends the
-// whole block back to the one-lane-per-sub-block decoder after the segmented
-// attempt, which costs more than it saves.
-constexpr bool kSegmentedDecode = false;
+constexpr uint32_t kOverlapBits = 768;
+constexpr uint32_t kSnapBits = 2048;          // segment boundaries this close to a sub-block's end move past it        // bits a segment decoder reads ahead of its start to synchronise
+constexpr bool kSegmentedDecode = true;
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
 
 // status codes (same values as the public header)
@@ -192,7 +189,7 @@ struct Misc {
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
-constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8;
+constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8, kSegRep = 16;
 struct Seg {
   uint32_t sub_start[kSubMax + 1];  // first payload bit of each sub-block; [n_sub] = payload bits
   uint32_t sub_end[kSubMax];        // bit after each sub-block's end symbol
@@ -202,7 +199,11 @@ struct Seg {
   uint32_t tail[kMaxLanes];                       // literals after a lane's last record, run still open
   uint32_t flags[kMaxLanes];                      // kSeg* bits
   uint32_t entry_sub[kMaxLanes];                  // sub-block of the lane's entry
-  uint32_t rec_base[kMaxLanes], lit_base[kMaxLanes], carry[kMaxLanes];
+  uint32_t nlog[kMaxLanes];                       // symbol boundaries the lane logged
+  uint32_t maybe_idx[kMaxLanes];                  // its record closing its first sub-block (kSegMaybe)
+  uint32_t rep_rec[kMaxLanes], rep_lit[kMaxLanes], rep_run[kMaxLanes];     // repair of the lane's start
+  uint32_t skip_rec[kMaxLanes], skip_lit[kMaxLanes], skip_run[kMaxLanes];  // own tokens it replaces
+  uint32_t eff_tail[kMaxLanes];                   // literals after the lane's last record, after repair
   uint32_t bad;
 };
 
@@ -542,6 +543,7 @@ struct SegLane {
   uint32_t cap_rec, cap_lit;
   GMEM uint64_t* rec_out;
   GMEM uint8_t* lit_out;
+  GMEM uint32_t* log;           // the first kLogN literal/length symbol boundaries from the entry
 };
 
 template <int kDec>
@@ -645,24 +647,42 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   }
   const uint32_t entry = pos, entry_sub = sb;
   uint32_t flags = (sb < n_sub && pos != s_seg.sub_start[sb]) ? kSegMid : 0u;
-  bool first_piece = (flags & kSegMid) != 0;
-  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0;
+  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0, nlog = 0, maybe_idx = 0;
   bool any_eob = false, fail = false;
   if (sb < n_sub && pos < g.p_end) {
+    g.log[nlog++] = pos;
     for (;;) {
       bool is_end = false;
       for (;;) {
         peek(state, n, kind, val);
-        advance(n);
-        pos += n;
         const bool is_dist = state != 0;
         const bool is_lit = !is_dist && kind == kKindLit;
         const bool is_len = !is_dist && kind == kKindLen;
         is_end = !is_dist && kind == kKindEnd;
-        bool bad = n == 0 || pos > sub_end;
-        bad = bad || (is_dist && (plen > max_match || val > window || sc >= g.cap_rec)) || (is_lit && lc >= g.cap_lit);
-        if (is_dist && !bad) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
-        if (is_lit && !bad) g.lit_out[lc] = (uint8_t)val;
+        const uint32_t np = pos + n;
+        const bool bad = n == 0 || np > sub_end || (is_dist && (plen > max_match || val > window)) ||
+                         (is_end && np != sub_end);
+        if (bad) {
+          // before the lane's first sub-block end and within its log, a bad
+          // symbol means the decoder is still out of step: move on one bit
+          // (a repair from the previous lane's exit replaces this stretch)
+          if (!any_eob && nlog < kLogN && pos < sub_end) {
+            advance(1);
+            pos += 1;
+            state = 0;
+            continue;
+          }
+          fail = true;
+          break;
+        }
+        advance(n);
+        pos = np;
+        if ((is_dist && sc >= g.cap_rec) || (is_lit && lc >= g.cap_lit)) {
+          fail = true;
+          break;
+        }
+        if (is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+        if (is_lit) g.lit_out[lc] = (uint8_t)val;
         sc += is_dist ? 1u : 0u;
         lc += is_lit ? 1u : 0u;
         pseq += is_dist ? 1u : 0u;
@@ -671,30 +691,27 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         run = is_dist ? 0u : run + (is_lit ? 1u : 0u);
         plen = is_len ? val : plen;
         state = is_len ? 1u : 0u;
-        if (bad) {
-          fail = true;
-          break;
-        }
+        if (state == 0 && !is_end && nlog < kLogN) g.log[nlog++] = pos;
         if (is_end || (state == 0 && pos >= g.p_end)) break;
       }
-      if (fail) break;
-      if (!is_end) break;  // reached the segment's end inside sub-block sb
-      // sub-block sb ends here: its end symbol must end exactly at its length
-      if (pos != sub_end) {
-        fail = true;
-        break;
-      }
-      if (run || (first_piece && sc == 0)) {
-        // the literal run the end closes is a sequence without a match; with
-        // no literals of its own, a lane's first such sequence only exists if
-        // the previous lanes' trailing literals flow into it (decided later)
+      if (fail || !is_end) break;  // failed, or reached the segment's end inside sub-block sb
+      // sub-block sb ends here.  The literal run the end closes is a sequence
+      // without a match.  At the lane's first end such a sequence is always
+      // written, even with no literals of its own: trailing literals of
+      // earlier lanes (or of a repair) may flow into it; if none do, it is
+      // dropped when the tokens are packed.
+      if (run || !any_eob) {
         if (sc >= g.cap_rec) {
           fail = true;
           break;
         }
         g.rec_out[sc] = (uint64_t)run;
-        if (run) pseq++;
-        else flags |= kSegMaybe;
+        if (run) {
+          pseq++;
+        } else {
+          flags |= kSegMaybe;
+          maybe_idx = sc;
+        }
         sc++;
       }
       any_eob = true;
@@ -702,13 +719,13 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       atomicAdd(&s_seg.cnt_lit[sb], plit);
       atomicAdd(&s_seg.cnt_raw[sb], praw);
       pseq = plit = praw = run = 0;
-      first_piece = false;
       sb++;
       pos = s_seg.sub_start[sb];
       state = 0;
       if (sb >= n_sub || pos >= g.p_end) break;
       sub_end = s_seg.sub_end[sb];
       load(pos);
+      if (nlog < kLogN) g.log[nlog++] = pos;
     }
     if (!fail && sb < n_sub && (pseq | plit | praw)) {
       atomicAdd(&s_seg.cnt_seq[sb], pseq);
@@ -725,6 +742,154 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   s_seg.tail[L] = run;
   s_seg.flags[L] = flags;
   s_seg.entry_sub[L] = entry_sub;
+  s_seg.nlog[L] = nlog;
+  s_seg.maybe_idx[L] = maybe_idx;
+  s_seg.rep_rec[L] = s_seg.rep_lit[L] = s_seg.rep_run[L] = 0;
+  s_seg.skip_rec[L] = s_seg.skip_lit[L] = s_seg.skip_run[L] = 0;
+}
+
+// Repair of lane k's start when its entry is not the previous lane's exit:
+// the previous lane's exit is exact, so decoding from there (slowly, straight
+// from HBM) follows the true path; the first literal/length boundary on it that
+// lane k also passed (its log) is where the two agree, and lane k's tokens
+// from there on are correct.  The repair's tokens replace lane k's tokens
+// before that point, and the sub-block's counts are corrected to match.
+struct SlowBits {
+  const GMEM uint8_t* payload;
+  uint32_t pw, k0, w0, w1, w2;
+  __device__ uint32_t word(uint32_t k) const { return k < pw ? gload32(payload + 4ull * k) : 0u; }
+  __device__ void at(uint32_t pos, uint32_t& lo, uint32_t& hi) {
+    const uint32_t k = pos >> 5;
+    if (k != k0) {
+      if (k == k0 + 1) {
+        w0 = w1;
+        w1 = w2;
+        w2 = word(k + 2);
+      } else {
+        w0 = word(k);
+        w1 = word(k + 1);
+        w2 = word(k + 2);
+      }
+      k0 = k;
+    }
+    lo = __builtin_amdgcn_alignbit(w1, w0, pos & 31);
+    hi = __builtin_amdgcn_alignbit(w2, w1, pos & 31);
+  }
+  __device__ void peek(uint32_t pos, uint32_t state, uint32_t lmask, uint32_t& n, uint32_t& kind, uint32_t& val) {
+    uint32_t lo, hi;
+    at(pos, lo, hi);
+    const uint32_t e = s_big[(state << kLutBits) | (lo & lmask)];
+    n = e & 31u;
+    const uint32_t x = (e >> 5) & 15u;
+    kind = (e >> 9) & 3u;
+    val = (e >> 16) + __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi, lo, n), 0, x);
+    n += x;
+  }
+};
+
+__device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const GMEM uint8_t* payload, uint32_t pw,
+                            uint32_t lmax,
+                            uint32_t window, uint32_t max_match, GMEM uint64_t* rep_rec_out,
+                            GMEM uint8_t* rep_lit_out) {
+  const uint32_t lmask = (1u << lmax) - 1u;
+  const uint32_t X = s_seg.exit_at[k - 1], E = s_seg.entry[k], sb = s_seg.entry_sub[k];
+  const uint32_t nlog = s_seg.nlog[k];
+  if (sb >= n_sub || nlog == 0 || X < s_seg.sub_start[sb] || X >= s_seg.sub_end[sb]) {
+    s_seg.bad = 1;
+    return;
+  }
+  const uint32_t sub_end = s_seg.sub_end[sb];
+  // the true path from X, until it meets lane k's path
+  SlowBits b{payload, pw, 0xFFFFFFFFu, 0u, 0u, 0u};
+  uint32_t pos = X, state = 0, plen = 0, rsc = 0, rlc = 0, rraw = 0, run = 0, j = 0;
+  uint32_t lg = g.log[0];
+  bool met = false;
+  for (uint32_t it = 0; it < 4 * kLogN + 64; it++) {
+    if (state == 0) {
+      while (j < nlog && lg < pos) {
+        j++;
+        lg = j < nlog ? g.log[j] : kDone;
+      }
+      if (j >= nlog) break;
+      if (lg == pos) {
+        met = true;
+        break;
+      }
+    }
+    uint32_t n, kind, val;
+    b.peek(pos, state, lmask, n, kind, val);
+    const bool is_dist = state != 0;
+    const bool is_lit = !is_dist && kind == kKindLit;
+    const bool is_len = !is_dist && kind == kKindLen;
+    const bool is_end = !is_dist && kind == kKindEnd;
+    if (n == 0 || is_end || pos + n > sub_end || (is_dist && (plen > max_match || val > window))) break;
+    if ((is_dist && rsc >= kRepRec) || (is_lit && rlc >= kRepLit)) break;
+    if (is_dist) {
+      rep_rec_out[rsc++] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+      rraw += plen;
+      run = 0;
+    }
+    if (is_lit) {
+      rep_lit_out[rlc++] = (uint8_t)val;
+      rraw++;
+      run++;
+    }
+    plen = is_len ? val : plen;
+    state = is_len ? 1u : 0u;
+    pos += n;
+  }
+  if (!met) {
+    s_seg.bad = 1;
+    return;
+  }
+  const uint32_t q = pos;
+  // lane k's own path from its entry to q, under the same rules as its decoder
+  uint32_t p2 = E, st2 = 0, pl2 = 0, sc = 0, lc = 0, raw = 0, run2 = 0;
+  for (uint32_t it = 0; p2 < q && it < 8 * kLogN + 1024; it++) {
+    uint32_t n, kind, val;
+    b.peek(p2, st2, lmask, n, kind, val);
+    const bool is_dist = st2 != 0;
+    const bool is_lit = !is_dist && kind == kKindLit;
+    const bool is_len = !is_dist && kind == kKindLen;
+    const bool is_end = !is_dist && kind == kKindEnd;
+    const uint32_t np = p2 + n;
+    const bool bad = n == 0 || np > sub_end || (is_dist && (pl2 > max_match || val > window)) ||
+                     (is_end && np != sub_end);
+    if (bad) {
+      if (p2 >= sub_end) break;
+      p2 += 1;
+      st2 = 0;
+      continue;
+    }
+    if (is_end) break;  // lane k passed a sub-block end before meeting the true path
+    if (is_dist) {
+      sc++;
+      raw += pl2;
+      run2 = 0;
+    }
+    if (is_lit) {
+      lc++;
+      raw++;
+      run2++;
+    }
+    pl2 = is_len ? val : pl2;
+    st2 = is_len ? 1u : 0u;
+    p2 = np;
+  }
+  if (p2 != q || st2 != 0) {
+    s_seg.bad = 1;
+    return;
+  }
+  atomicAdd(&s_seg.cnt_seq[sb], rsc - sc);
+  atomicAdd(&s_seg.cnt_lit[sb], rlc - lc);
+  atomicAdd(&s_seg.cnt_raw[sb], rraw - raw);
+  s_seg.rep_rec[k] = rsc;
+  s_seg.rep_lit[k] = rlc;
+  s_seg.rep_run[k] = run;
+  s_seg.skip_rec[k] = sc;
+  s_seg.skip_lit[k] = lc;
+  s_seg.skip_run[k] = run2;
+  s_seg.flags[k] |= kSegRep;
 }
 
 // ---------------------------------------------------------------- ring helpers
@@ -1265,6 +1430,21 @@ __device__ void flush_output(const LzArgs& a) {
 }
 
 // ---------------------------------------------------------------- A0/A2 segmented
+// A segment boundary that falls close to a sub-block's end moves to the next
+// sub-block's start (an exact symbol boundary): a decoder starting there has
+// nothing to synchronise, while one starting just before the end could stay
+// out of step until the end and then have no symbol boundary to meet.
+__device__ __forceinline__ uint32_t snap_boundary(uint32_t p, uint32_t n_sub) {
+  uint32_t lo = 0, hi = n_sub - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (s_seg.sub_start[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t e = s_seg.sub_end[lo];
+  return (p != s_seg.sub_start[lo] && (p >= e || e - p < kSnapBits)) ? s_seg.sub_start[lo + 1] : p;
+}
+
 // The segmented form of A2 for a block that qualifies: its index is
 // consistent, it has at most kSubMax sub-blocks, its payload gives every lane
 // at least two 16-byte rows, and its workspace holds the private areas.
@@ -1280,8 +1460,8 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   const uint32_t t = threadIdx.x, wave = t >> 6;
   const uint32_t pw = payload / 4;  // payload words (a multiple of 4)
   const uint64_t fin = final_bytes(n_seq, n_lit);
-  const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, kLanes);
-  const uint64_t lane_bytes = 8 * cap_rec + cap_lit;
+  const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, job.comp_len, kLanes);
+  const uint64_t lane_bytes = 8 * cap_rec + cap_lit + kLaneExtra;
   if (!kSegmentedDecode || n_sub == 0 || n_sub > kSubMax || pw < 8 * kLanes || payload >= (1u << 28) ||
       job.ws_len < fin + kLanes * lane_bytes)
     return false;
@@ -1325,16 +1505,16 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   SegLane g;
   if (t < kLanes) {
     const uint32_t rows = pw / 4;
-    const uint32_t r0 = (uint32_t)((uint64_t)rows * t / kLanes), r1 = (uint32_t)((uint64_t)rows * (t + 1) / kLanes);
-    g.p_begin = 128 * r0;
-    g.p_end = 128 * r1;
+    g.p_begin = snap_boundary(128 * (uint32_t)((uint64_t)rows * t / kLanes), n_sub);
+    g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
     const uint32_t warm = g.p_begin > kOverlapBits ? g.p_begin - kOverlapBits : 0u;
     g.base_word = (warm / 32) & ~3u;
-    g.n_words = min(pw, 4 * r1 + 8) - g.base_word;
+    g.n_words = min(pw, g.p_end / 32 + 8) - g.base_word;
     g.cap_rec = (uint32_t)cap_rec;
     g.cap_lit = (uint32_t)cap_lit;
     g.rec_out = (GMEM uint64_t*)(priv + lane_bytes * t);
     g.lit_out = priv + lane_bytes * t + 8 * cap_rec;
+    g.log = (GMEM uint32_t*)(g.lit_out + cap_lit);
     sh.sub_woff[t] = g.base_word;
     sh.sub_nw[t] = g.n_words;
     sh.rd[t] = 0;
@@ -1348,23 +1528,55 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     lds_release(&sh.rd[t], kDone);
   }
   __syncthreads();
-  // consistency: lanes meet, runs of literals carried across lane boundaries
-  uint32_t skip = 0, carry_in = 0, flags = 0;
+  // lanes whose entry is not the previous lane's exit: repair their start
+  GMEM uint64_t* rep_rec_out = nullptr;
+  GMEM uint8_t* rep_lit_out = nullptr;
+  if (t < kLanes) {
+    rep_rec_out = (GMEM uint64_t*)(g.log + kLogN);
+    rep_lit_out = (GMEM uint8_t*)(rep_rec_out + kRepRec);
+    if (t > 0 && !(s_seg.flags[t] & kSegFail) && !(s_seg.flags[t - 1] & kSegFail) &&
+        s_seg.entry[t] != s_seg.exit_at[t - 1])
+      repair_lane(g, t, n_sub, payload_bytes, pw, lmax, window, max_match, rep_rec_out, rep_lit_out);
+  }
+  __syncthreads();
+  // Each lane's effective token stream: its repair's tokens (if any), then its
+  // own tokens from the meeting point.  Literal runs that stay open at a
+  // lane's end flow into the next lanes' first sequence.
+  uint32_t flags = 0, rsc = 0, rlc = 0, sq = 0, lq = 0, nrec = 0, nlit = 0;
+  bool mid = false;
   if (t < kLanes) {
     flags = s_seg.flags[t];
-    bool ok = !(flags & kSegFail) && s_seg.entry[t] == (t ? s_seg.exit_at[t - 1] : 0u) &&
-              (t + 1 < kLanes || s_seg.exit_at[t] == 32 * pw);
-    if (flags & kSegMid) {
+    rsc = s_seg.rep_rec[t];
+    rlc = s_seg.rep_lit[t];
+    sq = s_seg.skip_rec[t];
+    lq = s_seg.skip_lit[t];
+    nrec = s_seg.nrec[t];
+    nlit = s_seg.nlit[t];
+    const uint32_t own_after = nrec - sq;
+    s_seg.eff_tail[t] = own_after ? s_seg.tail[t] : s_seg.rep_run[t] + s_seg.tail[t] - s_seg.skip_run[t];
+    const uint32_t eb = s_seg.entry_sub[t];
+    const uint32_t start = (flags & kSegRep) ? s_seg.exit_at[t - 1] : s_seg.entry[t];
+    mid = eb < n_sub && start != s_seg.sub_start[eb];
+    const bool meets = t == 0 ? s_seg.entry[0] == 0u : ((flags & kSegRep) || s_seg.entry[t] == s_seg.exit_at[t - 1]);
+    if ((flags & kSegFail) || !meets || (t + 1 == kLanes && s_seg.exit_at[t] != 32 * pw)) s_seg.bad = 1;
+  }
+  __syncthreads();
+  uint32_t carry_in = 0, own_fix = 0, drop = kDone;
+  if (t < kLanes) {
+    if (mid) {
       for (uint32_t j = t; j-- > 0;) {
-        carry_in += s_seg.tail[j];
-        if (!(s_seg.flags[j] & kSegPass)) break;
+        carry_in += s_seg.eff_tail[j];
+        if (s_seg.rep_rec[j] + s_seg.nrec[j] - s_seg.skip_rec[j] != 0) break;  // j has a sequence: the run starts there
       }
-    } else if (t && s_seg.tail[t - 1]) {
-      ok = false;  // an open literal run must continue in the next lane
+    } else if (t && s_seg.eff_tail[t - 1]) {
+      s_seg.bad = 1;  // an open literal run must continue in the next lane
     }
-    if ((flags & kSegMaybe) && carry_in) atomicAdd(&s_seg.cnt_seq[s_seg.entry_sub[t]], 1u);
-    skip = (flags & kSegMaybe) && !carry_in ? 1u : 0u;
-    if (!ok) s_seg.bad = 1;
+    own_fix = (rsc ? 0u : carry_in) + s_seg.rep_run[t] - s_seg.skip_run[t];
+    if (flags & kSegMaybe) {
+      const uint32_t mi = s_seg.maybe_idx[t];
+      if (mi == sq && own_fix) atomicAdd(&s_seg.cnt_seq[s_seg.entry_sub[t]], 1u);  // literals flow into it
+      else drop = mi;                                                            // an empty sequence: dropped
+    }
   }
   __syncthreads();
   for (uint32_t s = t; s < n_sub; s += kThreads) {
@@ -1373,41 +1585,62 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   __syncthreads();
   if (s_seg.bad) return false;
-  // pack the private areas into the final token stream
+  // pack the effective streams into the final token stream
   uint32_t v[4] = {0, 0, 0, 0}, tot[4];
   if (t < kLanes) {
-    v[0] = s_seg.nrec[t] - skip;
-    v[1] = s_seg.nlit[t];
+    v[0] = rsc + (nrec - sq) - (drop != kDone ? 1u : 0u);
+    v[1] = rlc + (nlit - lq);
   }
   block_excl_scan4<kThreads>(v, tot);
   if (tot[0] != n_seq || tot[1] != n_lit) return false;  // cannot happen once the counts matched
   if (t < kLanes) {
-    const uint32_t nrec = s_seg.nrec[t], nlit = s_seg.nlit[t];
+    GMEM uint64_t* rd = ws_seq + v[0];
+    // literal-run corrections are modulo 2^32 on the literal length (the low
+    // word): the match fields above it must not see a carry or a borrow
+    auto add_lit = [](uint64_t r, uint32_t d) { return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + d); };
+    for (uint32_t i = 0; i < rsc; i++) rd[i] = i == 0 ? add_lit(rep_rec_out[0], carry_in) : rep_rec_out[i];
+    rd += rsc;
     const GMEM uint64_t* rs = g.rec_out;
-    GMEM uint64_t* rd = ws_seq + v[0] - skip;
-    for (uint32_t i = skip; i < nrec; i += 16) {
+    for (uint32_t i = sq; i < nrec; i += 16) {
       uint64_t r[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) r[j] = i + j < nrec ? rs[i + j] : 0ull;
-      if (i == skip) r[0] += carry_in;  // literals of earlier lanes that open this lane's first sequence
+      if (i == sq) r[0] = add_lit(r[0], own_fix);
 #pragma unroll
-      for (int j = 0; j < 16; j++)
-        if (i + j < nrec) rd[i + j] = r[j];
+      for (int j = 0; j < 16; j++) {
+        const uint32_t x = i + j;
+        if (x < nrec && x != drop) rd[x - sq - (x > drop && drop != kDone ? 1u : 0u)] = r[j];
+      }
     }
-    const GMEM uint8_t* ls = g.lit_out;
     GMEM uint8_t* ld = ws_lit + v[1];
-    for (uint32_t i = 0; i < nlit; i += 64) {
+    for (uint32_t i = 0; i < rlc; i++) ld[i] = rep_lit_out[i];
+    ld += rlc;
+    const GMEM uint8_t* ls = g.lit_out + lq;
+    const uint32_t nl = nlit - lq;
+    for (uint32_t i = 0; i < nl; i += 64) {
       uint4 q[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) q[j] = i + 16 * j < nlit ? gload16(ls + i + 16 * j) : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
       for (int j = 0; j < 4; j++) {
         const uint32_t k = i + 16 * j;
-        if (k + 16 <= nlit) {
+        q[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (k < nl) {
+          if ((lq & 15) == 0) {
+            q[j] = gload16(ls + k);
+          } else {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t bb = 0; bb < 16 && k + bb < nl; bb++) w[bb / 4] |= (uint32_t)ls[k + bb] << (8 * (bb % 4));
+            q[j] = make_uint4(w[0], w[1], w[2], w[3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint32_t k = i + 16 * j;
+        if (k + 16 <= nl) {
           gstore16(ld + k, q[j]);
-        } else if (k < nlit) {
+        } else if (k < nl) {
           const uint32_t w[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
-          for (uint32_t b = 0; k + b < nlit; b++) ld[k + b] = (uint8_t)(w[b / 4] >> (8 * (b % 4)));
+          for (uint32_t bb = 0; k + bb < nl; bb++) ld[k + bb] = (uint8_t)(w[bb / 4] >> (8 * (bb % 4)));
         }
       }
     }

@@ -329,7 +329,7 @@ extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
     j.out = req->d_out + (uint64_t)b * bs;
     j.out_len = info.raw_len;
     j.ws = nullptr;
-    j.ws_len = gmpk::workspace_bytes(info.n_seq, info.n_lit);
+    j.ws_len = gmpk::workspace_bytes(info.n_seq, info.n_lit, o1 - o0);
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = req->d_status + b;

@@ -62,6 +62,6 @@ def test_stream_info_long_block_table(hip_lib_built):
 
 def test_workspace_bytes_covers_token_stream(hip_lib_built):
     import paper_1606_00519_amd as gmp
-    for n_seq, n_lit in ((0, 0), (1, 0), (130000, 260000), (5, 1 << 20)):
-        ws = gmp.workspace_bytes(n_seq, n_lit)
+    for n_seq, n_lit, comp in ((0, 0, 256), (1, 0, 300), (130000, 260000, 360000), (5, 1 << 20, 1 << 20)):
+        ws = gmp.workspace_bytes(n_seq, n_lit, comp)
         assert ws >= 8 * n_seq + n_lit + 64 and ws % 256 == 0

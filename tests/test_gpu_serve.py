@@ -101,7 +101,7 @@ def test_small_budget_back_pressure(ctx):
         ws = 0
         for blk, _ in oracle.stream_blocks(r.stream)[0]:
             i = gmp.block_info(blk)
-            ws += gmp.workspace_bytes(i["n_seq"], i["n_lit"])
+            ws += gmp.workspace_bytes(i["n_seq"], i["n_lit"], len(blk))
         sizes.append(len(r.stream) + len(r.raw) + ws)
     budget = int(max(sizes) * 1.5)
     srv = gmp.Server(ctx, budget_bytes=budget, workspace_bytes=budget, slots=4)
