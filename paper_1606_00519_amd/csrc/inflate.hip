@@ -653,6 +653,11 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
     g.log[nlog++] = pos;
     for (;;) {
       bool is_end = false;
+      // One symbol per step, branch-free apart from the stores.  A bad symbol
+      // before the lane's first sub-block end and within its log means the
+      // decoder is still out of step: it then moves on by one bit instead
+      // (a repair from the previous lane's exit replaces this stretch).
+      const bool can_nudge = !any_eob;
       for (;;) {
         peek(state, n, kind, val);
         const bool is_dist = state != 0;
@@ -662,37 +667,29 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         const uint32_t np = pos + n;
         const bool bad = n == 0 || np > sub_end || (is_dist && (plen > max_match || val > window)) ||
                          (is_end && np != sub_end);
-        if (bad) {
-          // before the lane's first sub-block end and within its log, a bad
-          // symbol means the decoder is still out of step: move on one bit
-          // (a repair from the previous lane's exit replaces this stretch)
-          if (!any_eob && nlog < kLogN && pos < sub_end) {
-            advance(1);
-            pos += 1;
-            state = 0;
-            continue;
-          }
+        const bool nudge = bad && can_nudge && nlog < kLogN && pos < sub_end;
+        const bool over = !bad && ((is_dist && sc >= g.cap_rec) || (is_lit && lc >= g.cap_lit));
+        const bool go = !bad && !over;
+        const uint32_t adv = go ? n : 1u;
+        advance(adv);
+        pos += adv;
+        if (go && is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+        if (go && is_lit) g.lit_out[lc] = (uint8_t)val;
+        const bool gd = go && is_dist, gl = go && is_lit;
+        sc += gd ? 1u : 0u;
+        lc += gl ? 1u : 0u;
+        pseq += gd ? 1u : 0u;
+        plit += gl ? 1u : 0u;
+        praw += gd ? plen : (gl ? 1u : 0u);
+        run = gd ? 0u : run + (gl ? 1u : 0u);
+        plen = (go && is_len) ? val : plen;
+        state = (go && is_len) ? 1u : 0u;
+        if (go && state == 0 && !is_end && nlog < kLogN) g.log[nlog++] = pos;
+        if ((bad && !nudge) || over) {
           fail = true;
           break;
         }
-        advance(n);
-        pos = np;
-        if ((is_dist && sc >= g.cap_rec) || (is_lit && lc >= g.cap_lit)) {
-          fail = true;
-          break;
-        }
-        if (is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
-        if (is_lit) g.lit_out[lc] = (uint8_t)val;
-        sc += is_dist ? 1u : 0u;
-        lc += is_lit ? 1u : 0u;
-        pseq += is_dist ? 1u : 0u;
-        plit += is_lit ? 1u : 0u;
-        praw += is_dist ? plen : (is_lit ? 1u : 0u);
-        run = is_dist ? 0u : run + (is_lit ? 1u : 0u);
-        plen = is_len ? val : plen;
-        state = is_len ? 1u : 0u;
-        if (state == 0 && !is_end && nlog < kLogN) g.log[nlog++] = pos;
-        if (is_end || (state == 0 && pos >= g.p_end)) break;
+        if (go && (is_end || (state == 0 && pos >= g.p_end))) break;
       }
       if (fail || !is_end) break;  // failed, or reached the segment's end inside sub-block sb
       // sub-block sb ends here.  The literal run the end closes is a sequence
