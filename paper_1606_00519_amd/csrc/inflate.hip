@@ -90,8 +90,8 @@ constexpr uint32_t kCoopLits = 64;            // longer literal runs are copied 
 constexpr uint32_t kTightPolls = 64;          // polls of a hand-over counter before pausing between polls
 constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
 constexpr uint32_t kSubMax = 512;             // most sub-blocks of a block decoded in segments
-constexpr uint32_t kOverlapBits = 768;
-constexpr uint32_t kSnapBits = 2048;          // segment boundaries this close to a sub-block's end move past it        // bits a segment decoder reads ahead of its start to synchronise
+constexpr uint32_t kOverlapBits = 768;        // bits a segment decoder reads ahead of its start to synchronise
+constexpr uint32_t kSnapBits = 2048;          // segment boundaries this close to a sub-block's end move past it
 constexpr bool kSegmentedDecode = true;
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
 
@@ -647,7 +647,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   }
   const uint32_t entry = pos, entry_sub = sb;
   uint32_t flags = (sb < n_sub && pos != s_seg.sub_start[sb]) ? kSegMid : 0u;
-  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0, nlog = 0, maybe_idx = 0;
+  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
   bool any_eob = false, fail = false;
   if (sb < n_sub && pos < g.p_end) {
     g.log[nlog++] = pos;
@@ -665,31 +665,39 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         const bool is_len = !is_dist && kind == kKindLen;
         is_end = !is_dist && kind == kKindEnd;
         const uint32_t np = pos + n;
-        const bool bad = n == 0 || np > sub_end || (is_dist && (plen > max_match || val > window)) ||
-                         (is_end && np != sub_end);
-        const bool nudge = bad && can_nudge && nlog < kLogN && pos < sub_end;
-        const bool over = !bad && ((is_dist && sc >= g.cap_rec) || (is_lit && lc >= g.cap_lit));
-        const bool go = !bad && !over;
+        // bitwise, not short-circuit, logic: the compiler keeps it branch-free
+        const bool bad = (n == 0) | (np > sub_end) | (is_dist & ((plen > max_match) | (val > window))) |
+                         (is_end & (np != sub_end));
+        const bool nudge = bad & can_nudge & (nlog < kLogN) & (pos < sub_end);
+        const bool over = !bad & ((is_dist & (sc >= g.cap_rec)) | (is_lit & (lc >= g.cap_lit)));
+        const bool go = !bad & !over;
         const uint32_t adv = go ? n : 1u;
         advance(adv);
         pos += adv;
-        if (go && is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
-        if (go && is_lit) g.lit_out[lc] = (uint8_t)val;
-        const bool gd = go && is_dist, gl = go && is_lit;
+        if (go & is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+        // literal bytes collect in a register and leave four at a time (the
+        // private area is 16-byte aligned); a partial word is written when
+        // the lane's decoding ends
+        const bool gd = go & is_dist, gl = go & is_lit;
+        lbuf = gl ? (lbuf | (val << (8 * (lc & 3)))) : lbuf;
+        if (gl && (lc & 3) == 3) {
+          reinterpret_cast<GMEM uint32_t*>(g.lit_out)[lc >> 2] = lbuf;
+          lbuf = 0;
+        }
         sc += gd ? 1u : 0u;
         lc += gl ? 1u : 0u;
         pseq += gd ? 1u : 0u;
         plit += gl ? 1u : 0u;
         praw += gd ? plen : (gl ? 1u : 0u);
         run = gd ? 0u : run + (gl ? 1u : 0u);
-        plen = (go && is_len) ? val : plen;
-        state = (go && is_len) ? 1u : 0u;
-        if (go && state == 0 && !is_end && nlog < kLogN) g.log[nlog++] = pos;
-        if ((bad && !nudge) || over) {
+        plen = (go & is_len) ? val : plen;
+        state = (go & is_len) ? 1u : 0u;
+        if (go & (state == 0) & !is_end & (nlog < kLogN)) g.log[nlog++] = pos;
+        if ((bad & !nudge) | over) {
           fail = true;
           break;
         }
-        if (go && (is_end || (state == 0 && pos >= g.p_end))) break;
+        if (go & (is_end | ((state == 0) & (pos >= g.p_end)))) break;
       }
       if (fail || !is_end) break;  // failed, or reached the segment's end inside sub-block sb
       // sub-block sb ends here.  The literal run the end closes is a sequence
@@ -730,6 +738,8 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       atomicAdd(&s_seg.cnt_raw[sb], praw);
     }
   }
+  // the last 1-3 literal bytes
+  for (uint32_t i = lc & ~3u; i < lc; i++) g.lit_out[i] = (uint8_t)(lbuf >> (8 * (i & 3)));
   if (fail) flags |= kSegFail;
   if (sc == 0 && !any_eob) flags |= kSegPass;
   s_seg.entry[L] = entry;
