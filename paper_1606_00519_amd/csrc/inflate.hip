@@ -1022,41 +1022,47 @@ __device__ __forceinline__ uint4 lit_read16(uint32_t p) {
 }
 
 // Window/ring accesses that are known not to wrap (the common case).
-__device__ __forceinline__ void write_upto16(uint8_t* d, uint4 v, uint32_t n) {
-  if (n == 16) {
-    __builtin_memcpy(d, &v, 16);
-    return;
-  }
-  uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32), hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
-  if (n & 8) {
-    __builtin_memcpy(d, &lo, 8);
-    d += 8;
-    lo = hi;
-  }
-  if (n & 4) {
-    const uint32_t w = (uint32_t)lo;
-    __builtin_memcpy(d, &w, 4);
-    d += 4;
-    lo >>= 32;
-  }
-  if (n & 2) {
-    const uint16_t h = (uint16_t)lo;
-    __builtin_memcpy(d, &h, 2);
-    d += 2;
-    lo >>= 16;
-  }
-  if (n & 1) *d = (uint8_t)lo;
-}
 __device__ __forceinline__ uint4 read16(const uint8_t* p) {
   uint4 v;
   __builtin_memcpy(&v, p, 16);
   return v;
 }
+// Copy n bytes from q to d, where no byte written is one that is read.
+// Any length takes two overlapping stores of one width (16, 8, 4 or 2
+// bytes: the first and the last bytes of the span), plus whole 16-byte chunks
+// in the middle of a copy longer than 32 bytes; a byte covered twice gets the
+// same value both times.  This keeps the lanes of a wavefront, whose lengths
+// differ, on few distinct paths.
+template <typename T>
+__device__ __forceinline__ void copy_pair(uint8_t* d, const uint8_t* q, uint32_t n) {
+  T a, b;
+  __builtin_memcpy(&a, q, sizeof(T));
+  __builtin_memcpy(&b, q + n - sizeof(T), sizeof(T));
+  __builtin_memcpy(d, &a, sizeof(T));
+  __builtin_memcpy(d + n - sizeof(T), &b, sizeof(T));
+}
+__device__ __forceinline__ void copy_bytes(uint8_t* d, const uint8_t* q, uint32_t n) {
+  if (n >= 16) {
+    const uint4 h = read16(q), t = read16(q + n - 16);
+    for (uint32_t k = 16; k + 16 < n; k += 16) {
+      const uint4 m = read16(q + k);
+      __builtin_memcpy(d + k, &m, 16);
+    }
+    __builtin_memcpy(d, &h, 16);
+    __builtin_memcpy(d + n - 16, &t, 16);
+  } else if (n >= 8) {
+    copy_pair<uint64_t>(d, q, n);
+  } else if (n >= 4) {
+    copy_pair<uint32_t>(d, q, n);
+  } else if (n >= 2) {
+    copy_pair<uint16_t>(d, q, n);
+  } else if (n) {
+    *d = *q;
+  }
+}
 // copy len bytes (dst - src >= len) inside the window, no wrap
 __device__ __forceinline__ void copy_nowrap(uint8_t* ring, uint32_t dst, uint32_t src, uint32_t len) {
-  uint8_t* d = ring + (dst & kRingMask);
-  const uint8_t* q = ring + (src & kRingMask);
-  for (uint32_t k = 0; k < len; k += 16) write_upto16(d + k, read16(q + k), min(16u, len - k));
+  copy_bytes(ring + (dst & kRingMask), ring + (src & kRingMask), len);
 }
 
 // Rare paths that read literal bytes straight from HBM (literal groups larger
@@ -1279,11 +1285,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       if (max_l > kCoopLits) {
         coop_lits(pos, lsrc, valid ? L : 0u, s_misc.coop[w]);
       } else if (plain) {
-        if (valid && L) {
-          uint8_t* d = ring + (pos & kRingMask);
-          const uint8_t* q = lit_ring() + (lsrc & (kLitRing - 1));
-          for (uint32_t k = 0; k < L; k += 16) write_upto16(d + k, read16(q + k), min(16u, L - k));
-        }
+        if (valid && L) copy_bytes(ring + (pos & kRingMask), lit_ring() + (lsrc & (kLitRing - 1)), L);
       } else if (valid && L) {
         for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
       }
