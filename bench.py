@@ -400,7 +400,7 @@ def main() -> int:
     ap.add_argument("--size-mib", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--waves", type=int, default=4, choices=(1, 2, 4),
+    ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
                     help="decoder (phase A) and resolver (phase B) wavefronts per block")
     ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serving: requests per load level (0 = skip)")

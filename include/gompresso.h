@@ -107,9 +107,11 @@ typedef struct {
 /* Tuning of the batched kernel (section "Dependency on Data Block Size":
  * sub-block count sets the Huffman parallelism per block). */
 typedef struct {
-  uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2 or 4 (Huffman lanes = 64 x waves); they
-                               also resolve back-references, groups round-robin.  Each workgroup adds a
-                               fetcher wavefront (HBM -> LDS) and a flusher wavefront (output -> HBM) */
+  uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2, 4 or 7 (Huffman lanes = 64 x waves);
+                               they also resolve back-references, groups round-robin.  Each workgroup adds
+                               a fetcher wavefront (HBM -> LDS) and, for 1, 2 or 4, a flusher wavefront
+                               (output -> HBM); with 7 (eight wavefronts, two per SIMD) the seventh decoder
+                               flushes and six resolve */
   uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
   uint32_t workgroups;      /* persistent grid size (0 = one per compute unit) */
   uint32_t reserved;
@@ -176,7 +178,7 @@ gmp_status gmp_batch_graph_launch(gmp_ctx* ctx, gmp_batch* batch, void* stream);
 /* ---- autotuner ---------------------------------------------------------------- */
 /* Choose launch parameters for a batch by timing candidates on the device
  * (section "Dependency on Data Block Size": parallelism per block against
- * per-block overheads): wavefronts per block in {1, 2, 4} x {one workgroup per
+ * per-block overheads): wavefronts per block in {1, 2, 4, 7} x {one workgroup per
  * job, persistent with one or two workgroups per compute unit}.  Each candidate
  * runs once untimed, then `reps` (1..64) timed runs on `stream`; the least
  * median wins.  The batch's outputs are overwritten (with the same bytes, for

@@ -348,7 +348,7 @@ gmp_status launch_params(const gmp_batch* b, const gmp_tuning* tuning, Launch* l
     x.persistent = tuning->persistent;
     x.workgroups = tuning->workgroups;
   }
-  if (x.waves != 1 && x.waves != 2 && x.waves != 4) return GMP_EINVAL;
+  if (x.waves != 1 && x.waves != 2 && x.waves != 4 && x.waves != 7) return GMP_EINVAL;
   if (x.persistent > 1) return GMP_EINVAL;
   if (x.persistent && x.workgroups == 0) x.workgroups = (uint32_t)b->num_cu;
   *l = x;
@@ -418,7 +418,7 @@ extern "C" gmp_status gmp_autotune(gmp_ctx* c, gmp_batch* b, uint32_t flags, uin
   HIP_OK(hipSetDevice(b->device));
   const hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<Launch> cands;
-  for (uint32_t w : {1u, 2u, 4u}) {
+  for (uint32_t w : {1u, 2u, 4u, 7u}) {
     cands.push_back({w, 0u, 0u});
     cands.push_back({w, 1u, (uint32_t)b->num_cu});
     cands.push_back({w, 1u, 2u * (uint32_t)b->num_cu});

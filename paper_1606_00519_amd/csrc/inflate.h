@@ -11,7 +11,7 @@
 
 namespace gmpk {
 
-constexpr int kMaxDecWaves = 4;  // decoder wavefronts per workgroup (plus one fetcher)
+constexpr int kMaxDecWaves = 7;  // decoder wavefronts per workgroup: 1, 2, 4 or 7
 
 // One block to decode (device copy of a host job, 80 bytes).
 struct DevJob {

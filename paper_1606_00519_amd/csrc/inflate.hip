@@ -168,6 +168,33 @@ __device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
 }
 
 constexpr int kMaxLanes = 64 * kMaxDecWaves;
+// Workgroup shape.  kDec decoder wavefronts (they resolve in phase B) and a
+// fetcher, plus a flusher of its own for kDec in {1, 2, 4}.  At kDec = 7 the
+// workgroup has eight wavefronts, two per SIMD: phase A decodes on seven,
+// and in phase B the seventh decoder flushes while six resolve.
+template <int kDec>
+constexpr uint32_t block_waves() {
+  return kDec == 7 ? 8u : (uint32_t)kDec + 2u;
+}
+template <int kDec>
+constexpr uint32_t block_threads() {
+  return 64 * block_waves<kDec>();
+}
+template <int kDec>
+constexpr uint32_t flusher_wave() {
+  return kDec == 7 ? 6u : (uint32_t)kDec + 1u;
+}
+template <int kDec>
+constexpr int resolver_waves() {
+  return (int)block_waves<kDec>() - 2;  // wavefronts 0 .. resolver_waves() - 1
+}
+// 16-byte rows of each decoder lane's bit ring: the largest power of two
+// the staging area holds for all lanes
+constexpr uint32_t pow2_floor(uint32_t x) { return x < 2 ? 1u : 2u * pow2_floor(x / 2); }
+template <int kDec>
+constexpr uint32_t ring_rows() {
+  return pow2_floor(kStageBytes / 16 / (64 * kDec));
+}
 
 struct Misc {
   uint8_t lens[kNumLL + kNumD];
@@ -374,7 +401,7 @@ __device__ __forceinline__ void block_excl_scan4(uint32_t v[4], uint32_t tot[4])
 // has taken, and publishes how many words are present.
 template <int kDec>
 __device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
-  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  constexpr uint32_t kLanes = 64 * kDec, kRows = ring_rows<kDec>();
   const uint32_t f = lane_id();
   uint32_t total[kDec], woff[kDec], fetched[kDec];
 #pragma unroll
@@ -442,7 +469,7 @@ struct SubBlock {
 // that is taken only when the fetcher is behind; errors end the lane's loop.
 template <int kDec>
 __device__ int decode_subblock(const SubBlock& sb, uint32_t L, uint32_t lmax, uint32_t window, uint32_t max_match) {
-  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  constexpr uint32_t kLanes = 64 * kDec, kRows = ring_rows<kDec>();
   static_assert((kRows & (kRows - 1)) == 0, "ring rows must be a power of two");
   if (sb.bit_len == 0) return kESUB;
   const uint32_t lmask = (1u << lmax) - 1u;
@@ -546,10 +573,26 @@ struct SegLane {
   GMEM uint32_t* log;           // the first kLogN literal/length symbol boundaries from the entry
 };
 
+// The sub-block holding payload bit p, and the first bit a lane whose segment
+// starts at p decodes: kOverlapBits before p, but not before that sub-block's
+// start (where decoding is exact from the first bit).
+__device__ __forceinline__ uint32_t sub_of(uint32_t p, uint32_t n_sub) {
+  uint32_t lo = 0, hi = n_sub - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (s_seg.sub_start[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ uint32_t warm_start(uint32_t p, uint32_t sb) {
+  return p >= s_seg.sub_start[sb] + kOverlapBits ? p - kOverlapBits : s_seg.sub_start[sb];
+}
+
 template <int kDec>
 __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uint32_t lmax, uint32_t window,
                                uint32_t max_match) {
-  constexpr uint32_t kLanes = 64 * kDec, kRows = kStageBytes / 16 / kLanes;
+  constexpr uint32_t kLanes = 64 * kDec, kRows = ring_rows<kDec>();
   const uint32_t lmask = (1u << lmax) - 1u;
   const uint32_t nw = g.n_words;
   const uint32_t* ring_base = reinterpret_cast<const uint32_t*>(s_stage) + 4 * L;
@@ -605,15 +648,8 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
     nx = ring_word(rd);
     s_misc.rd[L] = rd - 4;
   };
-  // the sub-block holding p_begin
-  uint32_t lo_s = 0, hi_s = n_sub - 1;
-  while (lo_s < hi_s) {
-    const uint32_t mid = (lo_s + hi_s + 1) / 2;
-    if (s_seg.sub_start[mid] <= g.p_begin) lo_s = mid;
-    else hi_s = mid - 1;
-  }
-  uint32_t sb = lo_s;
-  uint32_t pos = g.p_begin >= s_seg.sub_start[sb] + kOverlapBits ? g.p_begin - kOverlapBits : s_seg.sub_start[sb];
+  uint32_t sb = sub_of(g.p_begin, n_sub);
+  uint32_t pos = warm_start(g.p_begin, sb);  // at most 3 words past base_word
   uint32_t sub_end = s_seg.sub_end[sb];
   uint32_t state = 0, n, kind, val;
   load(pos);
@@ -1444,12 +1480,7 @@ __device__ void flush_output(const LzArgs& a) {
 // nothing to synchronise, while one starting just before the end could stay
 // out of step until the end and then have no symbol boundary to meet.
 __device__ __forceinline__ uint32_t snap_boundary(uint32_t p, uint32_t n_sub) {
-  uint32_t lo = 0, hi = n_sub - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) / 2;
-    if (s_seg.sub_start[mid] <= p) lo = mid;
-    else hi = mid - 1;
-  }
+  const uint32_t lo = sub_of(p, n_sub);
   const uint32_t e = s_seg.sub_end[lo];
   return (p != s_seg.sub_start[lo] && (p >= e || e - p < kSnapBits)) ? s_seg.sub_start[lo + 1] : p;
 }
@@ -1464,7 +1495,7 @@ template <int kDec>
 __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, const GMEM uint8_t* payload_bytes,
                                  uint32_t n_sub, uint32_t n_seq, uint32_t n_lit, uint32_t payload, uint32_t lmax,
                                  uint32_t window, uint32_t max_match, GMEM uint64_t* ws_seq, GMEM uint8_t* ws_lit) {
-  constexpr uint32_t kThreads = 64 * (kDec + 2), kLanes = 64 * kDec;
+  constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
   const uint32_t pw = payload / 4;  // payload words (a multiple of 4)
@@ -1516,8 +1547,8 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     const uint32_t rows = pw / 4;
     g.p_begin = snap_boundary(128 * (uint32_t)((uint64_t)rows * t / kLanes), n_sub);
     g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
-    const uint32_t warm = g.p_begin > kOverlapBits ? g.p_begin - kOverlapBits : 0u;
-    g.base_word = (warm / 32) & ~3u;
+    // the lane's bit ring starts at the row of the first bit it decodes
+    g.base_word = (warm_start(g.p_begin, sub_of(g.p_begin, n_sub)) / 32) & ~3u;
     g.n_words = min(pw, g.p_end / 32 + 8) - g.base_word;
     g.cap_rec = (uint32_t)cap_rec;
     g.cap_lit = (uint32_t)cap_lit;
@@ -1667,7 +1698,7 @@ __device__ __forceinline__ void stamp(const DevJob& job, int i) {
 // kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR or GMPK_MODE_DE.
 template <int kDec, int kMode>
 __device__ void inflate_block(const DevJob& job, uint32_t flags) {
-  constexpr uint32_t kThreads = 64 * (kDec + 2), kLanes = 64 * kDec;
+  constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
   stamp(job, 0);
@@ -1821,14 +1852,15 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
     sh.done_upto = 0;
     sh.flushed = 0;
   }
-  if (t < kMaxDecWaves) sh.next_group[t] = t < kDec ? t : kDone;
+  constexpr int kRes = resolver_waves<kDec>();
+  if (t < kMaxDecWaves) sh.next_group[t] = t < (uint32_t)kRes ? t : kDone;
   __syncthreads();
   if (wave == kDec) {
-    fetch_tokens<kDec>(a);
-  } else if (wave == kDec + 1) {
+    fetch_tokens<kRes>(a);
+  } else if (wave == flusher_wave<kDec>()) {
     flush_output(a);
   } else {
-    resolve_groups<kDec>(a, wave);
+    resolve_groups<kRes>(a, wave);
   }
   __syncthreads();
   stamp(job, 3);
@@ -1836,7 +1868,7 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
 }
 
 template <int kDec, int kMode>
-__global__ __launch_bounds__(64 * (kDec + 2)) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
+__global__ __launch_bounds__(block_threads<kDec>()) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
                                                                   uint32_t flags) {
   if (blockIdx.x >= n_jobs) return;
   DevJob job = jobs[blockIdx.x];
@@ -1848,7 +1880,7 @@ __global__ __launch_bounds__(64 * (kDec + 2)) void inflate_kernel(const DevJob* 
 // the job table is exhausted; every workgroup exits once it draws an index
 // past the end.
 template <int kDec, int kMode>
-__global__ __launch_bounds__(64 * (kDec + 2)) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
+__global__ __launch_bounds__(block_threads<kDec>()) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
                                                                              uint32_t n_jobs, uint32_t flags,
                                                                              uint32_t* __restrict__ queue) {
   for (;;) {
@@ -1872,10 +1904,10 @@ void launch_one(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t 
                 uint32_t* d_queue, hipStream_t stream) {
   if (persistent) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, d_queue);
-    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(64 * (kDec + 2)), 0, stream,
+    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(block_threads<kDec>()), 0, stream,
                        d_jobs, n_jobs, flags, d_queue);
   } else {
-    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(64 * (kDec + 2)), 0, stream, d_jobs, n_jobs,
+    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(block_threads<kDec>()), 0, stream, d_jobs, n_jobs,
                        flags);
   }
 }
@@ -1903,6 +1935,7 @@ extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t
     case 1: rc = launch_mode<1>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
     case 2: rc = launch_mode<2>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
     case 4: rc = launch_mode<4>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
+    case 7: rc = launch_mode<7>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
     default: return -1;
   }
   if (rc) return rc;

@@ -271,7 +271,8 @@ extern "C" gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uin
   *out = nullptr;
   gmp_tuning t{1u, 0u, 0u, 0u};
   if (tuning) t = *tuning;
-  if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4) return GMP_EINVAL;
+  if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4 && t.waves_per_block != 7)
+    return GMP_EINVAL;
   if (t.persistent) return GMP_EINVAL;  // requests launch one workgroup per block
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GMP_EDEVICE;

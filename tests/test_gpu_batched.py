@@ -122,7 +122,7 @@ def test_autotune_choice_decodes(ctx):
     blocks, raws = mixed_blocks(n_items=40, seed=13)
     db = DeviceBatch(ctx, blocks)
     tuning, ms = db.batch.autotune(gmp.MODE_AUTO, reps=2)
-    assert tuning["waves"] in (1, 2, 4) and ms > 0
+    assert tuning["waves"] in (1, 2, 4, 7) and ms > 0
     if tuning["persistent"]:
         assert tuning["workgroups"] > 0
     torch.cuda.synchronize()
