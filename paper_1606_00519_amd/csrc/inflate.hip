@@ -1633,58 +1633,96 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   block_excl_scan4<kThreads>(v, tot);
   if (tot[0] != n_seq || tot[1] != n_lit) return false;  // cannot happen once the counts matched
+  // Each lane's stream parameters go to LDS (arrays no longer read), then the
+  // whole workgroup copies: thread i writes the final stream's records
+  // [8 i, 8 i + 8) and literal bytes [16 i, 16 i + 16), then those kThreads
+  // further on, finding the lane streams they come from in the offsets.
+  // Neighbouring threads so read and write neighbouring bytes.
   if (t < kLanes) {
-    GMEM uint64_t* rd = ws_seq + v[0];
-    // literal-run corrections are modulo 2^32 on the literal length (the low
-    // word): the match fields above it must not see a carry or a borrow
-    auto add_lit = [](uint64_t r, uint32_t d) { return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + d); };
-    for (uint32_t i = 0; i < rsc; i++) rd[i] = i == 0 ? add_lit(rep_rec_out[0], carry_in) : rep_rec_out[i];
-    rd += rsc;
-    const GMEM uint64_t* rs = g.rec_out;
-    for (uint32_t i = sq; i < nrec; i += 16) {
-      uint64_t r[16];
+    s_seg.entry[t] = v[0];         // first record of lane t's stream in the final stream
+    s_seg.exit_at[t] = v[1];       // its first literal byte there
+    s_seg.eff_tail[t] = carry_in;  // literal-run correction of its first repair record
+    s_seg.tail[t] = own_fix;       // ... of its first own record
+    s_seg.maybe_idx[t] = drop;     // its own record that is dropped (kDone: none)
+  }
+  __syncthreads();
+  // the lane stream holding final-stream index o (starts: its first indexes)
+  auto stream_of = [&](const uint32_t* starts, uint32_t o) {
+    uint32_t lo = 0, hi = kLanes - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) / 2;
+      if (starts[mid] <= o) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
+  // literal-run corrections are modulo 2^32 on the literal length (the low
+  // word): the match fields above it must not see a carry or a borrow
+  auto add_lit = [](uint64_t r, uint32_t d) { return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + d); };
+  const uint64_t rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;  // a lane area's repair records
+  auto record = [&](uint32_t s, uint32_t j) -> uint64_t {  // record j of lane s's stream
+    const GMEM uint8_t* area = priv + lane_bytes * s;
+    const uint32_t rs = s_seg.rep_rec[s];
+    if (j < rs) {
+      const uint64_t r = ((const GMEM uint64_t*)(area + rep_off))[j];
+      return j == 0 ? add_lit(r, s_seg.eff_tail[s]) : r;
+    }
+    const uint32_t first = s_seg.skip_rec[s], d = s_seg.maybe_idx[s];
+    uint32_t x = first + (j - rs);
+    if (d != kDone && x >= d) x++;
+    const uint64_t r = ((const GMEM uint64_t*)area)[x];
+    return x == first ? add_lit(r, s_seg.tail[s]) : r;
+  };
+  for (uint32_t o = 8 * t; o < n_seq; o += 8 * kThreads) {
+    uint32_t s = stream_of(s_seg.entry, o);
+    uint64_t r[8];
 #pragma unroll
-      for (int j = 0; j < 16; j++) r[j] = i + j < nrec ? rs[i + j] : 0ull;
-      if (i == sq) r[0] = add_lit(r[0], own_fix);
-#pragma unroll
-      for (int j = 0; j < 16; j++) {
-        const uint32_t x = i + j;
-        if (x < nrec && x != drop) rd[x - sq - (x > drop && drop != kDone ? 1u : 0u)] = r[j];
+    for (uint32_t k = 0; k < 8; k++) {
+      const uint32_t ok = o + k;
+      if (ok < n_seq) {
+        while (s + 1 < kLanes && s_seg.entry[s + 1] <= ok) s++;
+        r[k] = record(s, ok - s_seg.entry[s]);
       }
     }
-    GMEM uint8_t* ld = ws_lit + v[1];
-    for (uint32_t i = 0; i < rlc; i++) ld[i] = rep_lit_out[i];
-    ld += rlc;
-    const GMEM uint8_t* ls = g.lit_out + lq;
-    const uint32_t nl = nlit - lq;
-    for (uint32_t i = 0; i < nl; i += 64) {
-      uint4 q[4];
+    if (o + 8 <= n_seq) {
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const uint32_t k = i + 16 * j;
-        q[j] = make_uint4(0u, 0u, 0u, 0u);
-        if (k < nl) {
-          if ((lq & 15) == 0) {
-            q[j] = gload16(ls + k);
-          } else {
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
-            for (uint32_t bb = 0; bb < 16 && k + bb < nl; bb++) w[bb / 4] |= (uint32_t)ls[k + bb] << (8 * (bb % 4));
-            q[j] = make_uint4(w[0], w[1], w[2], w[3]);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const uint32_t k = i + 16 * j;
-        if (k + 16 <= nl) {
-          gstore16(ld + k, q[j]);
-        } else if (k < nl) {
-          const uint32_t w[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
-          for (uint32_t bb = 0; k + bb < nl; bb++) ld[k + bb] = (uint8_t)(w[bb / 4] >> (8 * (bb % 4)));
-        }
-      }
+      for (uint32_t k = 0; k < 8; k += 2)
+        gstore16((GMEM uint8_t*)(ws_seq + o + k), make_uint4((uint32_t)r[k], (uint32_t)(r[k] >> 32),
+                                                             (uint32_t)r[k + 1], (uint32_t)(r[k + 1] >> 32)));
+    } else {
+      for (uint32_t k = 0; o + k < n_seq; k++) ws_seq[o + k] = r[k];
     }
   }
+  const uint64_t rep_lit_off = rep_off + 8 * kRepRec;  // a lane area's repair literals
+  for (uint32_t o = 16 * t; o < n_lit; o += 16 * kThreads) {
+    const uint32_t n = min(16u, n_lit - o);
+    uint32_t s = stream_of(s_seg.exit_at, o);
+    const uint32_t base = s_seg.exit_at[s], end = s + 1 < kLanes ? s_seg.exit_at[s + 1] : n_lit;
+    const uint32_t rl = s_seg.rep_lit[s];
+    uint4 q;
+    if (n == 16 && o >= base + rl && o + 16 <= end) {
+      // all 16 bytes are lane s's own literals, in a row
+      q = gload16(priv + lane_bytes * s + 8 * cap_rec + s_seg.skip_lit[s] + (o - base - rl));
+    } else {
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+      for (uint32_t k = 0; k < n; k++) {
+        const uint32_t ok = o + k;
+        while (s + 1 < kLanes && s_seg.exit_at[s + 1] <= ok) s++;
+        const uint32_t j = ok - s_seg.exit_at[s], rj = s_seg.rep_lit[s];
+        const GMEM uint8_t* area = priv + lane_bytes * s;
+        const uint8_t b = j < rj ? area[rep_lit_off + j] : area[8 * cap_rec + s_seg.skip_lit[s] + (j - rj)];
+        w[k / 4] |= (uint32_t)b << (8 * (k % 4));
+      }
+      q = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    if (n == 16) {
+      gstore16(ws_lit + o, q);
+    } else {
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+      for (uint32_t k = 0; k < n; k++) ws_lit[o + k] = (uint8_t)(w[k / 4] >> (8 * (k % 4)));
+    }
+  }
+  __syncthreads();
   return true;
 }
 
