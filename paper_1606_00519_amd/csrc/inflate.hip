@@ -170,8 +170,10 @@ __device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
 constexpr int kMaxLanes = 64 * kMaxDecWaves;
 // Workgroup shape.  kDec decoder wavefronts (they resolve in phase B) and a
 // fetcher, plus a flusher of its own for kDec in {1, 2, 4}.  At kDec = 7 the
-// workgroup has eight wavefronts, two per SIMD: phase A decodes on seven,
-// and in phase B the seventh decoder flushes while six resolve.
+// workgroup has eight wavefronts, two per SIMD: phase A decodes on seven; in
+// phase B four resolve (one per SIMD: the copies on the resolution chain do
+// not share their SIMD with another resolver's preparation work), the
+// seventh decoder flushes and two rest.
 template <int kDec>
 constexpr uint32_t block_waves() {
   return kDec == 7 ? 8u : (uint32_t)kDec + 2u;
@@ -186,7 +188,7 @@ constexpr uint32_t flusher_wave() {
 }
 template <int kDec>
 constexpr int resolver_waves() {
-  return (int)block_waves<kDec>() - 2;  // wavefronts 0 .. resolver_waves() - 1
+  return kDec == 7 ? 4 : kDec;  // wavefronts 0 .. resolver_waves() - 1
 }
 // 16-byte rows of each decoder lane's bit ring: the largest power of two
 // the staging area holds for all lanes
@@ -1897,7 +1899,7 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
     fetch_tokens<kRes>(a);
   } else if (wave == flusher_wave<kDec>()) {
     flush_output(a);
-  } else {
+  } else if (wave < (uint32_t)kRes) {
     resolve_groups<kRes>(a, wave);
   }
   __syncthreads();
