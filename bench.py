@@ -108,6 +108,13 @@ def oracle_leg(size: int, threads: int, cpu_seconds: float):
     return data, streams, baseline
 
 
+def launch_shape(waves: int) -> str:
+    if waves == 7:
+        return ("one workgroup per block, 8 wavefronts: 7 decoders + fetcher (Huffman phase); "
+                "4 resolvers + fetcher + flusher (LZ77 phase)")
+    return f"one workgroup per block: {waves} decoder/resolver wavefront(s) + fetcher + flusher"
+
+
 # ----------------------------------------------------------------------------- GPU leg
 def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int, waves: int):
     import numpy as np
@@ -312,7 +319,8 @@ def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads
 
 
 # ----------------------------------------------------------------------------- serving leg
-def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threads: int, budget: int = 64 << 30):
+def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threads: int, waves: int,
+              budget: int = 64 << 30):
     """Poisson arrivals of requests (log-uniform 64 KiB-64 MiB, text or CSV,
     ordinary or DE) at offered loads of 10-90 % of the batched peak, admitted
     by the library's request loop within an HBM budget; the requests' buffers
@@ -350,7 +358,7 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
                      "status": torch.full((nb,), 99, dtype=torch.int32, device="cuda"), "raw": raw})
     torch.cuda.synchronize()
     mean_u = float(np.mean([len(r) for r in raws]))
-    srv = gmp.Server(ctx, budget_bytes=budget, slots=4, waves=4)
+    srv = gmp.Server(ctx, budget_bytes=budget, slots=4, waves=waves)
     rng = np.random.default_rng(synth.SERVE_SEED + 100)
     levels = []
     for rho in (0.1, 0.3, 0.5, 0.7, 0.9):
@@ -431,7 +439,7 @@ def main() -> int:
             batched = batched_leg(ctx, data, args.batch_items, min(args.steps, 5), 1, args.threads)
         if args.serve_requests > 0:
             peak = batched["GBps"] if batched else size / (kernel_ms["mrr"] / 1e3) / 1e9
-            serving = serve_leg(ctx, data, peak, args.serve_pool, args.serve_requests, args.threads)
+            serving = serve_leg(ctx, data, peak, args.serve_pool, args.serve_requests, args.threads, args.waves)
         ctx.close()
     raw_step = 2 * size
     ms_per_step = wall / args.steps * 1e3
@@ -458,7 +466,7 @@ def main() -> int:
         "config": {"workload": f"zipf-text {args.size_mib} MiB, 1 MiB blocks x 64 sub-blocks of 16 KiB, "
                                f"window 32 KiB, matches 3-258, lmax 12; one MRR stream and one DE stream of "
                                f"the same data per step",
-                   "raw_bytes_per_step": raw_step, "blocks_per_stream": n_blocks, "launch": f"one workgroup per block: {args.waves} decoder/resolver wave(s) + fetcher + flusher"},
+                   "raw_bytes_per_step": raw_step, "blocks_per_stream": n_blocks, "launch": launch_shape(args.waves)},
         "modes": modes,
         "roofline": {"bound": "hbm", "kernel": f"inflate_kernel ({dom})", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5),

@@ -225,7 +225,7 @@ class Server:
     tensor; the caller keeps them alive until the request's completion is polled."""
 
     def __init__(self, ctx: "Context", budget_bytes: int, workspace_bytes: int = 0, slots: int = 4,
-                 waves: int = 4):
+                 waves: int = 7):
         self.ctx = ctx
         t = Tuning(waves, 0, 0, 0)
         h = C.c_void_p()

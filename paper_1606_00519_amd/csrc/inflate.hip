@@ -685,7 +685,9 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   }
   const uint32_t entry = pos, entry_sub = sb;
   uint32_t flags = (sb < n_sub && pos != s_seg.sub_start[sb]) ? kSegMid : 0u;
-  uint32_t sc = 0, lc = 0, run = 0, plen = 0, pseq = 0, plit = 0, praw = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
+  // per sub-block tallies: records and literals since the part's start (sc0,
+  // lc0), and the match bytes of those records (mlen)
+  uint32_t sc = 0, lc = 0, run = 0, plen = 0, sc0 = 0, lc0 = 0, mlen = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
   bool any_eob = false, fail = false;
   if (sb < n_sub && pos < g.p_end) {
     g.log[nlog++] = pos;
@@ -718,15 +720,13 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         // the lane's decoding ends
         const bool gd = go & is_dist, gl = go & is_lit;
         lbuf = gl ? (lbuf | (val << (8 * (lc & 3)))) : lbuf;
-        if (gl && (lc & 3) == 3) {
+        if (gl & ((lc & 3) == 3)) {
           reinterpret_cast<GMEM uint32_t*>(g.lit_out)[lc >> 2] = lbuf;
           lbuf = 0;
         }
         sc += gd ? 1u : 0u;
         lc += gl ? 1u : 0u;
-        pseq += gd ? 1u : 0u;
-        plit += gl ? 1u : 0u;
-        praw += gd ? plen : (gl ? 1u : 0u);
+        mlen += gd ? plen : 0u;
         run = gd ? 0u : run + (gl ? 1u : 0u);
         plen = (go & is_len) ? val : plen;
         state = (go & is_len) ? 1u : 0u;
@@ -743,6 +743,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       // written, even with no literals of its own: trailing literals of
       // earlier lanes (or of a repair) may flow into it; if none do, it is
       // dropped when the tokens are packed.
+      uint32_t pseq = sc - sc0;
       if (run || !any_eob) {
         if (sc >= g.cap_rec) {
           fail = true;
@@ -759,9 +760,11 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       }
       any_eob = true;
       atomicAdd(&s_seg.cnt_seq[sb], pseq);
-      atomicAdd(&s_seg.cnt_lit[sb], plit);
-      atomicAdd(&s_seg.cnt_raw[sb], praw);
-      pseq = plit = praw = run = 0;
+      atomicAdd(&s_seg.cnt_lit[sb], lc - lc0);
+      atomicAdd(&s_seg.cnt_raw[sb], lc - lc0 + mlen);
+      sc0 = sc;
+      lc0 = lc;
+      mlen = run = 0;
       sb++;
       pos = s_seg.sub_start[sb];
       state = 0;
@@ -770,10 +773,10 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       load(pos);
       if (nlog < kLogN) g.log[nlog++] = pos;
     }
-    if (!fail && sb < n_sub && (pseq | plit | praw)) {
-      atomicAdd(&s_seg.cnt_seq[sb], pseq);
-      atomicAdd(&s_seg.cnt_lit[sb], plit);
-      atomicAdd(&s_seg.cnt_raw[sb], praw);
+    if (!fail && sb < n_sub && (sc - sc0 | lc - lc0)) {
+      atomicAdd(&s_seg.cnt_seq[sb], sc - sc0);
+      atomicAdd(&s_seg.cnt_lit[sb], lc - lc0);
+      atomicAdd(&s_seg.cnt_raw[sb], lc - lc0 + mlen);
     }
   }
   // the last 1-3 literal bytes
