@@ -1162,6 +1162,45 @@ struct LzArgs {
   uint32_t n_seq, n_lit, raw_len;
   bool single_pass;
   GMEM uint8_t* rounds;
+  // After segmented decoding the records are read from the lane areas
+  // (priv: the first area; null: from the packed stream in ws)
+  const GMEM uint8_t* priv;
+  uint64_t lane_bytes, rep_off;  // an area's size, and where its repair records start
+  uint32_t lanes;
+};
+
+// A fetcher lane's view of one lane stream of the segmented decoder: its
+// records are its repair's records, then its own from its meeting point,
+// less a dropped empty sequence; its first record takes the literal-run
+// correction, modulo 2^32 on the literal length (the low word).  The
+// parameters stay in registers while the lane's records come from one stream.
+struct StreamCursor {
+  uint32_t s = 0, begin = 0, end = 0;  // stream s holds final records [begin, end)
+  uint32_t rs = 0, first = 0, drop = kDone, fix_rep = 0, fix_own = 0;
+  const GMEM uint8_t* area = nullptr;
+  __device__ __forceinline__ void load(const LzArgs& a, uint32_t k) {
+    s = k;
+    begin = s_seg.entry[k];
+    end = k + 1 < a.lanes ? s_seg.entry[k + 1] : a.n_seq;
+    rs = s_seg.rep_rec[k];
+    first = s_seg.skip_rec[k];
+    drop = s_seg.maybe_idx[k];
+    fix_rep = s_seg.eff_tail[k];
+    fix_own = s_seg.tail[k];
+    area = a.priv + a.lane_bytes * k;
+  }
+  // record o (>= the previous one asked for)
+  __device__ __forceinline__ uint64_t record(const LzArgs& a, uint32_t o) {
+    while (o >= end && s + 1 < a.lanes) load(a, s + 1);
+    const uint32_t j = o - begin;
+    uint32_t x = first + (j - rs);
+    x += (drop != kDone && x >= drop) ? 1u : 0u;
+    const bool rep = j < rs;
+    const uint64_t off = rep ? a.rep_off + 8ull * j : 8ull * x;
+    const uint32_t fix = rep ? (j == 0 ? fix_rep : 0u) : (x == first ? fix_own : 0u);
+    const uint64_t r = *(const GMEM uint64_t*)(area + off);
+    return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + fix);
+  }
 };
 
 // Resolution runs as a pipeline over groups of 64 sequences.  Resolver
@@ -1190,6 +1229,8 @@ __device__ void fetch_tokens(const LzArgs& a) {
   const uint32_t rec_chunks = (a.n_seq + 127) / 128, lit_chunks = (a.n_lit + 1023) / 1024;
   const uint64_t lit_base = 8ull * a.n_seq;
   uint32_t rf = 0, lf = 0, tf = 0, carry_out = 0, carry_lit = 0;
+  StreamCursor cur;
+  if (a.priv) cur.load(a, 0);
   Spin sp;
   while (rf < rec_chunks || lf < lit_chunks) {
     uint32_t gmin = kDone;
@@ -1198,13 +1239,32 @@ __device__ void fetch_tokens(const LzArgs& a) {
     if (gmin == kDone) break;  // every resolver has finished
     // literal bytes before the first group still being read are consumed
     const uint32_t lit_cons = gmin < 2 * tf ? s_misc.g_lit[gmin % kGRing] : carry_lit;
-    uint32_t issued = 0;
-    while (rf < rec_chunks && 128ull * (rf + 1) <= 64ull * gmin + kRecRing && issued < 8) {
-      uint64_t o = 1024ull * rf + 16 * lane;
-      if (o + 16 > a.ws_len) o = a.ws_len - 16;
-      dma16(a.ws + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
-      rf++;
-      issued++;
+    uint32_t issued = 0, gathered = 0;
+    uint64_t g[8][2];
+    if (a.priv) {
+      // records gathered from the lane streams: lane l takes records 2l and
+      // 2l + 1 of up to eight 128-record chunks, loads first, stores after
+#pragma unroll
+      for (uint32_t c = 0; c < 8; c++) {
+        const uint32_t ch = rf + c;
+        if (ch < rec_chunks && 128ull * (ch + 1) <= 64ull * gmin + kRecRing && gathered == c) {
+#pragma unroll
+          for (uint32_t k = 0; k < 2; k++) {
+            const uint32_t o = 128 * ch + 2 * lane + k;
+            g[c][k] = o < a.n_seq ? cur.record(a, o) : 0ull;
+          }
+          gathered++;
+        }
+      }
+      issued = gathered;
+    } else {
+      while (rf < rec_chunks && 128ull * (rf + 1) <= 64ull * gmin + kRecRing && issued < 8) {
+        uint64_t o = 1024ull * rf + 16 * lane;
+        if (o + 16 > a.ws_len) o = a.ws_len - 16;
+        dma16(a.ws + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
+        rf++;
+        issued++;
+      }
     }
     while (lf < lit_chunks && 1024ull * (lf + 1) <= (uint64_t)lit_cons + kLitRing && issued < 12) {
       uint64_t o = lit_base + 1024ull * lf + 16 * lane;
@@ -1219,6 +1279,15 @@ __device__ void fetch_tokens(const LzArgs& a) {
     }
     sp = Spin();
     wait_all_memory();
+#pragma unroll
+    for (uint32_t c = 0; c < 8; c++) {
+      if (c < gathered) {
+        uint2* row = &rec_ring()[(128 * (rf + c)) % kRecRing];
+        row[2 * lane] = make_uint2((uint32_t)g[c][0], (uint32_t)(g[c][0] >> 32));
+        row[2 * lane + 1] = make_uint2((uint32_t)g[c][1], (uint32_t)(g[c][1] >> 32));
+      }
+    }
+    rf += gathered;
     // offsets of the two groups of every record chunk that arrived
     for (; tf < rf; tf++) {
       const uint32_t j = 128 * tf + 2 * lane;
@@ -1638,11 +1707,12 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   block_excl_scan4<kThreads>(v, tot);
   if (tot[0] != n_seq || tot[1] != n_lit) return false;  // cannot happen once the counts matched
-  // Each lane's stream parameters go to LDS (arrays no longer read), then the
-  // whole workgroup copies: thread i writes the final stream's records
-  // [8 i, 8 i + 8) and literal bytes [16 i, 16 i + 16), then those kThreads
-  // further on, finding the lane streams they come from in the offsets.
-  // Neighbouring threads so read and write neighbouring bytes.
+  // Each lane's stream parameters go to LDS (arrays no longer read).  The
+  // records stay in the lane areas: phase B's fetcher gathers them from
+  // there (gather_records).  The literals are packed by the whole
+  // workgroup: thread i writes the final stream's bytes [16 i, 16 i + 16),
+  // then those kThreads further on, finding the lane streams they come from
+  // in the offsets, so neighbouring threads read and write neighbouring bytes.
   if (t < kLanes) {
     s_seg.entry[t] = v[0];         // first record of lane t's stream in the final stream
     s_seg.exit_at[t] = v[1];       // its first literal byte there
@@ -1661,43 +1731,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     }
     return lo;
   };
-  // literal-run corrections are modulo 2^32 on the literal length (the low
-  // word): the match fields above it must not see a carry or a borrow
-  auto add_lit = [](uint64_t r, uint32_t d) { return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + d); };
   const uint64_t rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;  // a lane area's repair records
-  auto record = [&](uint32_t s, uint32_t j) -> uint64_t {  // record j of lane s's stream
-    const GMEM uint8_t* area = priv + lane_bytes * s;
-    const uint32_t rs = s_seg.rep_rec[s];
-    if (j < rs) {
-      const uint64_t r = ((const GMEM uint64_t*)(area + rep_off))[j];
-      return j == 0 ? add_lit(r, s_seg.eff_tail[s]) : r;
-    }
-    const uint32_t first = s_seg.skip_rec[s], d = s_seg.maybe_idx[s];
-    uint32_t x = first + (j - rs);
-    if (d != kDone && x >= d) x++;
-    const uint64_t r = ((const GMEM uint64_t*)area)[x];
-    return x == first ? add_lit(r, s_seg.tail[s]) : r;
-  };
-  for (uint32_t o = 8 * t; o < n_seq; o += 8 * kThreads) {
-    uint32_t s = stream_of(s_seg.entry, o);
-    uint64_t r[8];
-#pragma unroll
-    for (uint32_t k = 0; k < 8; k++) {
-      const uint32_t ok = o + k;
-      if (ok < n_seq) {
-        while (s + 1 < kLanes && s_seg.entry[s + 1] <= ok) s++;
-        r[k] = record(s, ok - s_seg.entry[s]);
-      }
-    }
-    if (o + 8 <= n_seq) {
-#pragma unroll
-      for (uint32_t k = 0; k < 8; k += 2)
-        gstore16((GMEM uint8_t*)(ws_seq + o + k), make_uint4((uint32_t)r[k], (uint32_t)(r[k] >> 32),
-                                                             (uint32_t)r[k + 1], (uint32_t)(r[k + 1] >> 32)));
-    } else {
-      for (uint32_t k = 0; o + k < n_seq; k++) ws_seq[o + k] = r[k];
-    }
-  }
   const uint64_t rep_lit_off = rep_off + 8 * kRepRec;  // a lane area's repair literals
   for (uint32_t o = 16 * t; o < n_lit; o += 16 * kThreads) {
     const uint32_t n = min(16u, n_lit - o);
@@ -1889,6 +1923,14 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   a.raw_len = raw_len;
   a.single_pass = single_pass;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
+  a.priv = nullptr;
+  if (segmented) {
+    const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, job.comp_len, kLanes);
+    a.priv = gmem(job.ws) + final_bytes(n_seq, n_lit);
+    a.lane_bytes = 8 * cap_rec + cap_lit + kLaneExtra;
+    a.rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;
+    a.lanes = kLanes;
+  }
   if (t == 0) {
     sh.rec_avail = 0;
     sh.lit_avail = 0;
