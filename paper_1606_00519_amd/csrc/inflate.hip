@@ -731,11 +731,9 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         plen = (go & is_len) ? val : plen;
         state = (go & is_len) ? 1u : 0u;
         if (go & (state == 0) & !is_end & (nlog < kLogN)) g.log[nlog++] = pos;
-        if ((bad & !nudge) | over) {
-          fail = true;
-          break;
-        }
-        if (go & (is_end | ((state == 0) & (pos >= g.p_end)))) break;
+        // one exit for both ends of the loop (fewer lane masks to track)
+        fail = (bad & !nudge) | over;
+        if (fail | (go & (is_end | ((state == 0) & (pos >= g.p_end))))) break;
       }
       if (fail || !is_end) break;  // failed, or reached the segment's end inside sub-block sb
       // sub-block sb ends here.  The literal run the end closes is a sequence
@@ -1201,6 +1199,24 @@ struct StreamCursor {
     const uint64_t r = *(const GMEM uint64_t*)(area + off);
     return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + fix);
   }
+  // records o and o + 1: one 16-byte load when both are the stream's own
+  // records and lie side by side in its area (the usual case)
+  __device__ __forceinline__ void record2(const LzArgs& a, uint32_t o, uint64_t& r0, uint64_t& r1) {
+    while (o >= end && s + 1 < a.lanes) load(a, s + 1);
+    const uint32_t j = o - begin;
+    uint32_t x = first + (j - rs);
+    x += (drop != kDone && x >= drop) ? 1u : 0u;
+    if (o + 1 < end && j >= rs && x + 1 != drop) {
+      const GMEM uint32_t* p = (const GMEM uint32_t*)(area + 8ull * x);
+      const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
+      const uint32_t fix = x == first ? fix_own : 0u;
+      r0 = ((uint64_t)w1 << 32) | (uint32_t)(w0 + fix);
+      r1 = ((uint64_t)w3 << 32) | w2;
+    } else {
+      r0 = record(a, o);
+      r1 = o + 1 < a.n_seq ? record(a, o + 1) : 0ull;
+    }
+  }
 };
 
 // Resolution runs as a pipeline over groups of 64 sequences.  Resolver
@@ -1248,10 +1264,11 @@ __device__ void fetch_tokens(const LzArgs& a) {
       for (uint32_t c = 0; c < 8; c++) {
         const uint32_t ch = rf + c;
         if (ch < rec_chunks && 128ull * (ch + 1) <= 64ull * gmin + kRecRing && gathered == c) {
-#pragma unroll
-          for (uint32_t k = 0; k < 2; k++) {
-            const uint32_t o = 128 * ch + 2 * lane + k;
-            g[c][k] = o < a.n_seq ? cur.record(a, o) : 0ull;
+          const uint32_t o = 128 * ch + 2 * lane;
+          if (o < a.n_seq) {
+            cur.record2(a, o, g[c][0], g[c][1]);
+          } else {
+            g[c][0] = g[c][1] = 0ull;
           }
           gathered++;
         }
