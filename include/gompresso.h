@@ -142,7 +142,8 @@ gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks,
 /* Decode one block.  h_block: host copy of the block's header and index (the same
  * bytes as d_block, at least gmp_block_info.block_bytes - payload_bytes long), used
  * only to size the workspace.  d_status: device int32 that receives the block's
- * status.  Asynchronous on `stream`. */
+ * status.  Asynchronous on `stream`.  This call and gmp_decompress_stream launch one
+ * workgroup per block with seven decoder wavefronts (see gmp_tuning). */
 gmp_status gmp_decompress_block(gmp_ctx* ctx, const uint8_t* d_block, size_t block_len, const void* h_block,
                                 size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
                                 void* stream);

@@ -195,7 +195,9 @@ gmp_status ctx_reserve(gmp_ctx* c, size_t n_jobs, size_t ws_bytes) {
 
 gmp_status ctx_launch(gmp_ctx* c, size_t n_jobs, uint32_t flags, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(c->d_jobs, c->h_jobs, n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, s));
-  if (gmpk_launch(c->d_jobs, (uint32_t)n_jobs, flags, 1, 0, 0, c->d_queue, s) != 0) return GMP_EDEVICE;
+  // the single-block and single-stream calls use the workgroup shape the
+  // benchmark times: seven decoder wavefronts (two per SIMD)
+  if (gmpk_launch(c->d_jobs, (uint32_t)n_jobs, flags, 7, 0, 0, c->d_queue, s) != 0) return GMP_EDEVICE;
   HIP_OK(hipEventRecord(c->done, s));
   c->pending = true;
   return GMP_OK;

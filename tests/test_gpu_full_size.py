@@ -1,5 +1,6 @@
 """GPU parity at the full measured sizes, in the launch shape the benchmark
-times (one batch, one job per block, one decoder wave per block):
+times (one batch, one job per block, seven decoder wavefronts per block),
+and for the Zipf text also with one decoder wavefront per block:
 
 * 256 MiB of Zipf text, 1 MiB blocks of 64 x 16 KiB sub-blocks, 32 KiB
   window, matches 3..258, code lengths <= 12; ordinary and DE streams;
@@ -45,13 +46,14 @@ def corpus(name):
     return _data[name]
 
 
-@pytest.mark.parametrize("name,de", [(n, d) for n in CASES for d in (0, 1)])
-def test_full_size(ctx, name, de):
+@pytest.mark.parametrize("name,de,waves", [(n, d, 7) for n in CASES for d in (0, 1)] +
+                         [("zipf256", d, 1) for d in (0, 1)])
+def test_full_size(ctx, name, de, waves):
     data = corpus(name)
     p = oracle.CompressParams(window=32768, max_match=258, lmax=12, de=de, group=64, **CASES[name][2])
     s = oracle.compress(data, p, threads=16)
     flags = 2 if de else 1
-    st, out = decode_stream_batched(ctx, s, flags=flags, waves=1, persistent=False)
+    st, out = decode_stream_batched(ctx, s, flags=flags, waves=waves, persistent=False)
     assert np.all(st == 0), st[st != 0][:8]
     ref = np.frombuffer(data, np.uint8)
     bad = np.flatnonzero(out != ref)

@@ -185,7 +185,7 @@ def test_de_single_pass_rounds(ctx):
 
 # --------------------------------------------------------------------------- launch shapes
 
-@pytest.mark.parametrize("waves,persistent", [(1, False), (2, False), (4, False), (1, True), (2, True), (4, True)])
+@pytest.mark.parametrize("waves,persistent", [(w, p) for p in (False, True) for w in (1, 2, 4, 7)])
 def test_launch_shapes_agree(ctx, waves, persistent):
     data = synth.csv_rows(6 << 20).tobytes()
     blocks = []
