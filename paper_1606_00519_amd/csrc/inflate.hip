@@ -45,6 +45,10 @@ namespace gmpk {
 // that every access compiles to a global_* instruction: flat accesses would be
 // ordered against LDS traffic and force waits on both counters.
 #define GMEM __attribute__((address_space(1)))
+// four words at a 16-byte aligned address (one 16-byte access)
+struct __attribute__((aligned(16))) Aligned16 {
+  uint32_t x, y, z, w;
+};
 struct __attribute__((packed)) Packed16 {
   uint32_t x, y, z, w;
 };
@@ -688,6 +692,16 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // per sub-block tallies: records and literals since the part's start (sc0,
   // lc0), and the match bytes of those records (mlen)
   uint32_t sc = 0, lc = 0, run = 0, plen = 0, sc0 = 0, lc0 = 0, mlen = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
+  // records leave two at a time (16 bytes; the area is 16-byte aligned): an
+  // even-numbered record waits in rpend for the next one
+  uint64_t rpend = 0;
+  auto store_pair = [&](uint32_t i, uint64_t r0, uint64_t r1) {  // records i (even) and i + 1
+    GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.rec_out + i);
+    d->x = (uint32_t)r0;
+    d->y = (uint32_t)(r0 >> 32);
+    d->z = (uint32_t)r1;
+    d->w = (uint32_t)(r1 >> 32);
+  };
   bool any_eob = false, fail = false;
   if (sb < n_sub && pos < g.p_end) {
     g.log[nlog++] = pos;
@@ -714,11 +728,13 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         const uint32_t adv = go ? n : 1u;
         advance(adv);
         pos += adv;
-        if (go & is_dist) g.rec_out[sc] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
         // literal bytes collect in a register and leave four at a time (the
         // private area is 16-byte aligned); a partial word is written when
         // the lane's decoding ends
         const bool gd = go & is_dist, gl = go & is_lit;
+        const uint64_t rec = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
+        if (gd & ((sc & 1) != 0)) store_pair(sc - 1, rpend, rec);
+        rpend = (gd & ((sc & 1) == 0)) ? rec : rpend;
         lbuf = gl ? (lbuf | (val << (8 * (lc & 3)))) : lbuf;
         if (gl & ((lc & 3) == 3)) {
           reinterpret_cast<GMEM uint32_t*>(g.lit_out)[lc >> 2] = lbuf;
@@ -747,7 +763,8 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
           fail = true;
           break;
         }
-        g.rec_out[sc] = (uint64_t)run;
+        if (sc & 1) store_pair(sc - 1, rpend, (uint64_t)run);
+        else rpend = (uint64_t)run;
         if (run) {
           pseq++;
         } else {
@@ -777,7 +794,8 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       atomicAdd(&s_seg.cnt_raw[sb], lc - lc0 + mlen);
     }
   }
-  // the last 1-3 literal bytes
+  // the last record of an odd count, and the last 1-3 literal bytes
+  if (sc & 1) g.rec_out[sc - 1] = rpend;
   for (uint32_t i = lc & ~3u; i < lc; i++) g.lit_out[i] = (uint8_t)(lbuf >> (8 * (i & 3)));
   if (fail) flags |= kSegFail;
   if (sc == 0 && !any_eob) flags |= kSegPass;
