@@ -695,6 +695,8 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // records leave two at a time (16 bytes; the area is 16-byte aligned): an
   // even-numbered record waits in rpend for the next one
   uint64_t rpend = 0;
+  // literal words likewise wait for the rest of their 16 bytes (lw0..lw2)
+  uint32_t lw0 = 0, lw1 = 0, lw2 = 0;
   auto store_pair = [&](uint32_t i, uint64_t r0, uint64_t r1) {  // records i (even) and i + 1
     GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.rec_out + i);
     d->x = (uint32_t)r0;
@@ -728,16 +730,26 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         const uint32_t adv = go ? n : 1u;
         advance(adv);
         pos += adv;
-        // literal bytes collect in a register and leave four at a time (the
-        // private area is 16-byte aligned); a partial word is written when
-        // the lane's decoding ends
+        // literal bytes collect in a register, four to a word, and the words
+        // leave four at a time (the private area is 16-byte aligned); what
+        // is left is written when the lane's decoding ends
         const bool gd = go & is_dist, gl = go & is_lit;
         const uint64_t rec = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
         if (gd & ((sc & 1) != 0)) store_pair(sc - 1, rpend, rec);
         rpend = (gd & ((sc & 1) == 0)) ? rec : rpend;
         lbuf = gl ? (lbuf | (val << (8 * (lc & 3)))) : lbuf;
         if (gl & ((lc & 3) == 3)) {
-          reinterpret_cast<GMEM uint32_t*>(g.lit_out)[lc >> 2] = lbuf;
+          const uint32_t wi = (lc >> 2) & 3;
+          if (wi == 3) {
+            GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.lit_out + (lc & ~15u));
+            d->x = lw0;
+            d->y = lw1;
+            d->z = lw2;
+            d->w = lbuf;
+          }
+          lw0 = wi == 0 ? lbuf : lw0;
+          lw1 = wi == 1 ? lbuf : lw1;
+          lw2 = wi == 2 ? lbuf : lw2;
           lbuf = 0;
         }
         sc += gd ? 1u : 0u;
@@ -794,8 +806,14 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       atomicAdd(&s_seg.cnt_raw[sb], lc - lc0 + mlen);
     }
   }
-  // the last record of an odd count, and the last 1-3 literal bytes
+  // the last record of an odd count, the last whole literal words of an
+  // unfinished 16 bytes, and the last 1-3 literal bytes
   if (sc & 1) g.rec_out[sc - 1] = rpend;
+  GMEM uint32_t* lw = reinterpret_cast<GMEM uint32_t*>(g.lit_out + (lc & ~15u));
+  const uint32_t nlw = (lc >> 2) & 3;  // whole words since the last 16 bytes left
+  if (nlw > 0) lw[0] = lw0;
+  if (nlw > 1) lw[1] = lw1;
+  if (nlw > 2) lw[2] = lw2;
   for (uint32_t i = lc & ~3u; i < lc; i++) g.lit_out[i] = (uint8_t)(lbuf >> (8 * (i & 3)));
   if (fail) flags |= kSegFail;
   if (sc == 0 && !any_eob) flags |= kSegPass;
