@@ -695,8 +695,23 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // records leave two at a time (16 bytes; the area is 16-byte aligned): an
   // even-numbered record waits in rpend for the next one
   uint64_t rpend = 0;
-  // literal words likewise wait for the rest of their 16 bytes (lw0..lw2)
-  uint32_t lw0 = 0, lw1 = 0, lw2 = 0;
+  // literal words likewise wait for the rest of their 16 bytes (lw0..lw2),
+  // and log entries for the rest of theirs (lg0..lg2)
+  uint32_t lw0 = 0, lw1 = 0, lw2 = 0, lg0 = 0, lg1 = 0, lg2 = 0;
+  auto log_push = [&](uint32_t v) {
+    const uint32_t wi = nlog & 3;
+    if (wi == 3) {
+      GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.log + (nlog & ~3u));
+      d->x = lg0;
+      d->y = lg1;
+      d->z = lg2;
+      d->w = v;
+    }
+    lg0 = wi == 0 ? v : lg0;
+    lg1 = wi == 1 ? v : lg1;
+    lg2 = wi == 2 ? v : lg2;
+    nlog++;
+  };
   auto store_pair = [&](uint32_t i, uint64_t r0, uint64_t r1) {  // records i (even) and i + 1
     GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.rec_out + i);
     d->x = (uint32_t)r0;
@@ -706,7 +721,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   };
   bool any_eob = false, fail = false;
   if (sb < n_sub && pos < g.p_end) {
-    g.log[nlog++] = pos;
+    log_push(pos);
     for (;;) {
       bool is_end = false;
       // One symbol per step, branch-free apart from the stores.  A bad symbol
@@ -758,7 +773,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         run = gd ? 0u : run + (gl ? 1u : 0u);
         plen = (go & is_len) ? val : plen;
         state = (go & is_len) ? 1u : 0u;
-        if (go & (state == 0) & !is_end & (nlog < kLogN)) g.log[nlog++] = pos;
+        if (go & (state == 0) & !is_end & (nlog < kLogN)) log_push(pos);
         // one exit for both ends of the loop (fewer lane masks to track)
         fail = (bad & !nudge) | over;
         if (fail | (go & (is_end | ((state == 0) & (pos >= g.p_end))))) break;
@@ -798,7 +813,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       if (sb >= n_sub || pos >= g.p_end) break;
       sub_end = s_seg.sub_end[sb];
       load(pos);
-      if (nlog < kLogN) g.log[nlog++] = pos;
+      if (nlog < kLogN) log_push(pos);
     }
     if (!fail && sb < n_sub && (sc - sc0 | lc - lc0)) {
       atomicAdd(&s_seg.cnt_seq[sb], sc - sc0);
@@ -814,6 +829,10 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   if (nlw > 0) lw[0] = lw0;
   if (nlw > 1) lw[1] = lw1;
   if (nlw > 2) lw[2] = lw2;
+  GMEM uint32_t* lgw = g.log + (nlog & ~3u);  // the last log entries of an unfinished 16 bytes
+  if ((nlog & 3) > 0) lgw[0] = lg0;
+  if ((nlog & 3) > 1) lgw[1] = lg1;
+  if ((nlog & 3) > 2) lgw[2] = lg2;
   for (uint32_t i = lc & ~3u; i < lc; i++) g.lit_out[i] = (uint8_t)(lbuf >> (8 * (i & 3)));
   if (fail) flags |= kSegFail;
   if (sc == 0 && !any_eob) flags |= kSegPass;
