@@ -1506,8 +1506,13 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
           if (my_round == r) copy_nowrap(ring, dst, src0, M);
         }
       } else {
+        // only the copies that wrap or overlap their own output take the
+        // general routine; the others keep the plain one
         for (uint32_t r = 1; r <= rounds; r++) {
-          if (my_round == r) copy_match(ring, dst, M, D);
+          if (my_round == r) {
+            if (lane_plain) copy_nowrap(ring, dst, src0, M);
+            else copy_match(ring, dst, M, D);
+          }
         }
       }
       // its output is final once everything in front of it is
