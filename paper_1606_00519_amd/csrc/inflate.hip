@@ -1469,7 +1469,11 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       } else if (plain) {
         if (valid && L) copy_bytes(ring + (pos & kRingMask), lit_ring() + (lsrc & (kLitRing - 1)), L);
       } else if (valid && L) {
-        for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
+        // per lane: the plain copy unless this lane's run wraps a ring
+        if ((pos & kRingMask) + L <= kRing && (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing)
+          copy_bytes(ring + (pos & kRingMask), lit_ring() + (lsrc & (kLitRing - 1)), L);
+        else
+          for (uint32_t k = 0; k < L; k += 16) ring_write(ring, pos + k, lit_read16(lsrc + k), min(16u, L - k));
       }
       lds_release(&s_misc.next_group[w], g + kRes);
       const uint32_t dst = pos + L;
