@@ -409,7 +409,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
-                    help="decoder (phase A) and resolver (phase B) wavefronts per block")
+                    help="decoder wavefronts per block (phase A); with 7, four of them resolve in phase B")
     ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serving: requests per load level (0 = skip)")
     ap.add_argument("--serve-pool", type=int, default=192, help="serving: distinct device-resident requests")

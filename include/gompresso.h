@@ -110,8 +110,8 @@ typedef struct {
   uint32_t waves_per_block; /* decoder wavefronts per workgroup: 1, 2, 4 or 7 (Huffman lanes = 64 x waves);
                                they also resolve back-references, groups round-robin.  Each workgroup adds
                                a fetcher wavefront (HBM -> LDS) and, for 1, 2 or 4, a flusher wavefront
-                               (output -> HBM); with 7 (eight wavefronts, two per SIMD) the seventh decoder
-                               flushes and six resolve */
+                               (output -> HBM); with 7 (eight wavefronts, two per SIMD) four of the
+                               decoders resolve and the seventh flushes */
   uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
   uint32_t workgroups;      /* persistent grid size (0 = one per compute unit) */
   uint32_t reserved;
