@@ -69,13 +69,27 @@ typedef int32_t gmp_status;
 #define GMP_ESTALL -12  /* a device-side wait exceeded its time bound (about 1 s); the block's
                            output is incomplete.  An internal error: the kernel bounds every
                            wait so that a fault in its hand-over logic ends instead of hanging */
+/* Error classes on the device follow the order in which the decoder meets the
+ * problem, which is the order of the CPU reference decoder's checks for header,
+ * code-length and index errors.  Inside a bitstream the two decoders can meet
+ * different first errors, because the GPU decodes all sub-blocks at once: a
+ * corrupt bitstream always fails, with ECODE, EDIST, ELEN or ESUB. */
 
 /* flags */
 #define GMP_MODE_AUTO 0u  /* single pass if the block says DE and its group is a multiple of 64, else MRR */
 #define GMP_MODE_MRR 1u   /* Multi-Round Resolution for every block (valid for any stream) */
 #define GMP_MODE_DE 2u    /* single pass; blocks whose header is not DE with group % 64 == 0 fail EINVAL */
+#define GMP_MODE_SC 3u    /* Sequential Copying: the back-references of a group one after another, in
+                             sequence order (the baseline of the paper's section "Performance Impact of
+                             Nested back-references"; valid for any stream) */
 #define GMP_MODE_MASK 3u
-#define GMP_FLAG_STATS 0x100u /* record MRR rounds per 64-sequence group (gmp_job.d_rounds) */
+#define GMP_FLAG_STATS 0x100u /* record MRR rounds per 64-sequence group (gmp_job.d_rounds), phase times
+                                 (d_times) and counters (d_stats); batched calls only */
+#define GMP_FLAG_VERIFY_DE 0x200u /* check the Dependency Elimination rule (section "Dependency Elimination
+                                 (DE)") in every group of a DE block: every source must end at or before the
+                                 destination of the group's first back-reference.  Without the flag a group
+                                 that breaks the rule is still decoded correctly (by rounds); with it the
+                                 block's status is GMP_EDIST, as the CPU format check reports */
 
 typedef struct gmp_ctx gmp_ctx;
 typedef struct gmp_batch gmp_batch;
@@ -89,20 +103,34 @@ typedef struct {
 
 /* One block to decode.  The host fills n_seq / n_lit from gmp_block_info;
  * they size the token workspace.  With GMP_FLAG_STATS, d_rounds (may be NULL)
- * receives one byte per 64-sequence group: the MRR rounds taken (1 for a
- * single pass, 0 for a group without back-references; bit 7 set when the
- * group was split because its output exceeded the on-chip window), and
- * d_times (may be NULL) four device wall-clock stamps (100 MHz ticks): start,
- * tables built, sub-blocks decoded, back-references resolved. */
+ * receives one byte per 64-sequence group: the rounds taken (MRR rounds; 1
+ * for a single pass; the number of back-references under GMP_MODE_SC; 0 for
+ * a group without back-references; bit 7 set when the group was split
+ * because its output exceeded the on-chip window), d_times (may be NULL)
+ * four device wall-clock stamps (100 MHz ticks): start, tables built,
+ * sub-blocks decoded, back-references resolved, and d_stats (may be NULL)
+ * GMP_STATS_WORDS counters, laid out as the GMP_STAT_* indexes say. */
 typedef struct {
-  const uint8_t* d_comp; /* device: the block (header, index, payload) */
+  const uint8_t* d_comp; /* device: the block (header, index, payload), 16-byte aligned */
   uint64_t comp_len;     /* bytes readable at d_comp */
   uint8_t* d_out;        /* device: where the block's raw_len bytes go */
   uint64_t out_len;      /* must equal raw_len */
   uint32_t n_seq, n_lit; /* from the block header */
   uint8_t* d_rounds;     /* optional, ceil(n_seq/64) bytes */
   uint64_t* d_times;     /* optional, 4 x uint64 */
+  uint32_t* d_stats;     /* optional, GMP_STATS_WORDS x uint32 */
 } gmp_job;
+
+/* Counters of one block (gmp_job.d_stats, GMP_FLAG_STATS). */
+#define GMP_STATS_WORDS 80
+#define GMP_STAT_A2_PATH 0      /* how the Huffman stage ran: 1 segmented (the block's bits cut into equal
+                                   segments, one per decoder lane), 2 one lane per sub-block */
+#define GMP_STAT_REPAIRED 1     /* segmented: decoder lanes whose start had to be repaired */
+#define GMP_STAT_GROUPS 2       /* groups of 64 sequences */
+#define GMP_STAT_SPLIT 3        /* groups resolved in pieces (output larger than the on-chip window) */
+#define GMP_STAT_DE_ROUNDS 4    /* groups of a DE block that broke the DE rule and were resolved by rounds */
+#define GMP_STAT_ROUND_BYTES 16 /* [16 + r]: back-reference bytes copied in round r + 1, over all groups
+                                   (r < 64): the numerator of the paper's bytes-per-round measure */
 
 /* Tuning of the batched kernel (section "Dependency on Data Block Size":
  * sub-block count sets the Huffman parallelism per block). */
@@ -123,6 +151,14 @@ typedef struct {
 gmp_status gmp_ctx_create(int device, gmp_ctx** out);
 void gmp_ctx_destroy(gmp_ctx* ctx);
 const char* gmp_strerror(gmp_status s);
+/* First device-side error (section "Parallel Decompression": every block is
+ * decoded on the device, so its errors surface there).  Waits until the work
+ * queued on `stream` has finished, then moves to *h_first_error the first
+ * non-zero block status that any launch of this context recorded since the
+ * previous gmp_poll (its block, stream and batch calls, and its servers'
+ * launches), and clears it; GMP_OK there means none.  The per-block status
+ * words keep every block's own result.  Returns EDEVICE on a HIP error. */
+gmp_status gmp_poll(gmp_ctx* ctx, void* stream, int32_t* h_first_error);
 
 /* ---- host-side parsing ---------------------------------------------------------- */
 /* Parse a block header from a host copy of at least its first 208 + 16*n_sub bytes
@@ -139,10 +175,11 @@ gmp_status gmp_stream_info(const void* h_stream, size_t len, uint32_t* n_blocks,
                            uint64_t* raw_total);
 
 /* ---- single block (sections "Huffman Decoding" and "LZ77 Decompression") ---------- */
-/* Decode one block.  h_block: host copy of the block's header and index (the same
+/* Decode one block.  d_block: the block on the device, 16-byte aligned (EINVAL
+ * otherwise).  h_block: host copy of the block's header and index (the same
  * bytes as d_block, at least gmp_block_info.block_bytes - payload_bytes long), used
  * only to size the workspace.  d_status: device int32 that receives the block's
- * status.  Asynchronous on `stream`.  This call and gmp_decompress_stream launch one
+ * status.  flags: GMP_MODE_*, GMP_FLAG_VERIFY_DE.  Asynchronous on `stream`.  This call and gmp_decompress_stream launch one
  * workgroup per block with seven decoder wavefronts (see gmp_tuning). */
 gmp_status gmp_decompress_block(gmp_ctx* ctx, const uint8_t* d_block, size_t block_len, const void* h_block,
                                 size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
@@ -150,7 +187,8 @@ gmp_status gmp_decompress_block(gmp_ctx* ctx, const uint8_t* d_block, size_t blo
 
 /* ---- whole stream (blocks in parallel, section "Parallel Decompression") ----------- */
 /* Decode a stream.  h_stream: host copy of the whole stream (for the block table and
- * block headers); d_stream: the same bytes on the device.  d_status: n_blocks int32
+ * block headers); d_stream: the same bytes on the device, 16-byte aligned, with
+ * every block at a 16-byte aligned offset (EINVAL / EFORMAT otherwise).  d_status: n_blocks int32
  * on the device.  out_len must equal the stream's raw_total. */
 gmp_status gmp_decompress_stream(gmp_ctx* ctx, const uint8_t* d_stream, const void* h_stream, size_t len,
                                  uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags, void* stream);
@@ -195,16 +233,19 @@ gmp_status gmp_autotune(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, uint32_t
  * workspace) stay within `budget_bytes`; whenever one of its `n_slots` launch
  * slots (a HIP stream each, default priority) is free, it launches every
  * admitted request that is not running yet as one kernel over all their blocks
- * (one workgroup per block, largest first; blocks are independent, section
- * "Gompresso Overview").  Requests that arrive while others run join the next
- * launch, and launches of different slots overlap on the device.  When a launch
- * completes, its requests are reported and their budget is released.  Every
- * block is decoded in the mode its header names (GMP_MODE_AUTO); a request's
- * flags are checked at submission.  Compressed input, output and status words
- * belong to the caller and stay resident on the device; the server owns a
- * token-workspace arena of `workspace_bytes` (0 = budget / 2), handed out
- * first-fit.  A request whose bytes exceed the budget can never be admitted and
- * is refused by gmp_server_submit with GMP_EBUSY. */
+ * (one workgroup per block, largest first; one kernel per distinct request
+ * flags; blocks are independent, section "Gompresso Overview").  Requests that
+ * arrive while others run join the next launch, and launches of different
+ * slots overlap on the device.  Each request completes on its own: its blocks
+ * count themselves done in host-visible memory, and the request is reported,
+ * and its budget released, as soon as the last of them has finished.  Every
+ * block is decoded with its request's flags (GMP_MODE_*, GMP_FLAG_VERIFY_DE).
+ * Compressed input, output and status words belong to the caller and stay
+ * resident on the device; the server owns a token-workspace arena of
+ * `workspace_bytes` (0 = budget / 2), handed out first-fit.  A request whose
+ * bytes exceed the budget, or whose workspace exceeds the arena, can never be
+ * admitted and is refused by gmp_server_submit with GMP_EBUSY.  At most 4096
+ * requests are admitted at once. */
 typedef struct gmp_server gmp_server;
 
 typedef struct {
@@ -221,11 +262,11 @@ typedef struct {
 
 typedef struct {
   uint64_t tag;
-  int32_t status;          /* GMP_OK once the launch completed (per-block results are in d_status);
-                              else the host-side or HIP error that ended the request */
+  int32_t status;          /* GMP_OK once every block of the request has finished (per-block results
+                              are in d_status); else the host-side or HIP error that ended it */
   uint32_t reserved;
   uint64_t bytes;          /* decompressed bytes of the request */
-  uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* host steady clock */
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* host steady clock: submitted, launched, seen complete */
 } gmp_completion;
 
 typedef struct {
@@ -239,9 +280,10 @@ typedef struct {
 gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uint64_t workspace_bytes, uint32_t n_slots,
                              const gmp_tuning* tuning, gmp_server** out);
 /* Queue a request (thread-safe).  The header and block table are checked here:
- * EFORMAT / ESIZE / EINVAL as for gmp_decompress_stream (GMP_MODE_DE on a block
- * whose header is not DE with a group that is a multiple of 64 is EINVAL); EBUSY
- * if the request alone exceeds the budget. */
+ * EFORMAT / ESIZE / EINVAL as for gmp_decompress_stream (a d_stream that is not
+ * 16-byte aligned, or GMP_MODE_DE on a block whose header is not DE with a group
+ * that is a multiple of 64, is EINVAL); EBUSY if the request alone exceeds the
+ * budget or its workspace the arena. */
 gmp_status gmp_server_submit(gmp_server* srv, const gmp_request* req);
 /* Move up to `max` completions (in completion order) to `out`; returns how many. */
 uint32_t gmp_server_poll(gmp_server* srv, gmp_completion* out, uint32_t max);

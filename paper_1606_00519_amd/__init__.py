@@ -24,10 +24,14 @@ LIB_PATH = os.path.join(_HERE, "libgompresso_hip.so")
 
 OK, EINVAL, EFORMAT, ECODE, EDIST, ELEN, ESIZE, ESUB, EDEVICE, ENOMEM, EBUSY, ENOSYS, ESTALL = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12)
-MODE_AUTO, MODE_MRR, MODE_DE = 0, 1, 2
+MODE_AUTO, MODE_MRR, MODE_DE, MODE_SC = 0, 1, 2, 3
 FLAG_STATS = 0x100
+FLAG_VERIFY_DE = 0x200
+# per-block counters (gmp_job.d_stats)
+STATS_WORDS = 80
+STAT_A2_PATH, STAT_REPAIRED, STAT_GROUPS, STAT_SPLIT, STAT_DE_ROUNDS, STAT_ROUND_BYTES = 0, 1, 2, 3, 4, 16
 
-EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_block_info_parse", "gmp_stream_info",
+EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info",
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",
            "gmp_batch_destroy", "gmp_batch_graph_create", "gmp_batch_graph_launch", "gmp_autotune",
            "gmp_server_create", "gmp_server_submit", "gmp_server_poll", "gmp_server_drain", "gmp_server_stats",
@@ -47,7 +51,8 @@ class BlockInfo(C.Structure):
 
 class Job(C.Structure):
     _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("d_out", C.c_void_p), ("out_len", C.c_uint64),
-                ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p)]
+                ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p),
+                ("d_stats", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -82,6 +87,7 @@ def _load():
     L.gmp_ctx_destroy.restype = None
     L.gmp_strerror.argtypes = [i32]
     L.gmp_strerror.restype = C.c_char_p
+    L.gmp_poll.argtypes = [vp, vp, C.POINTER(i32)]
     L.gmp_block_info_parse.argtypes = [vp, sz, C.POINTER(BlockInfo)]
     L.gmp_stream_info.argtypes = [vp, sz, C.POINTER(u32), C.POINTER(u32), C.POINTER(C.c_uint64)]
     L.gmp_decompress_block.argtypes = [vp, vp, sz, vp, sz, vp, sz, vp, u32, vp]
@@ -103,7 +109,7 @@ def _load():
     L.gmp_workspace_bytes.restype = C.c_uint64
     L.gmp_server_destroy.argtypes = [vp]
     L.gmp_server_destroy.restype = None
-    for fn in ("gmp_ctx_create", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
+    for fn in ("gmp_ctx_create", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
                "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run", "gmp_batch_graph_create",
                "gmp_batch_graph_launch", "gmp_autotune", "gmp_server_create", "gmp_server_submit",
                "gmp_server_drain", "gmp_server_stats"):
@@ -319,3 +325,12 @@ class Context:
 
     def batch_create(self, jobs: list[Job], status) -> Batch:
         return Batch(self, jobs, status)
+
+    def poll(self, stream=None) -> int:
+        """First device-side error recorded by this context's launches since the last poll
+        (gmp_poll; waits for the work queued on `stream`); 0 if none."""
+        e = C.c_int32()
+        st = lib.gmp_poll(self.handle, _stream_handle(stream), C.byref(e))
+        if st:
+            raise GmpError(st, "gmp_poll")
+        return int(e.value)

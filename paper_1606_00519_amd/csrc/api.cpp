@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/gompresso.h"
+#include "host_internal.h"
 #include "inflate.h"
 
 namespace {
@@ -52,7 +53,9 @@ struct gmp_ctx {
   uint8_t* d_ws = nullptr;  // token workspace of the single-call paths
   size_t ws_cap = 0;
   uint32_t* d_queue = nullptr;
-  hipEvent_t done = nullptr;  // recorded after the last single-call launch
+  int32_t* d_first_err = nullptr;  // [0]: first device error since the last poll, [1]: poll staging
+  int32_t* h_poll = nullptr;       // pinned
+  hipEvent_t done = nullptr;       // recorded after the last single-call launch
   bool pending = false;
 };
 
@@ -62,6 +65,7 @@ struct gmp_batch {
   gmpk::DevJob* d_jobs = nullptr;
   uint8_t* d_ws = nullptr;
   uint32_t* d_queue = nullptr;
+  int32_t* d_first_err = nullptr;  // the context's first-error word
   int num_cu = 0;
   hipStream_t capture = nullptr;  // stream used for graph capture
   hipGraph_t graph = nullptr;
@@ -143,7 +147,9 @@ extern "C" gmp_status gmp_ctx_create(int device, gmp_ctx** out) {
   c->device = device;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&c->d_queue, 256) != hipSuccess) {
+      hipMalloc(&c->d_queue, 256) != hipSuccess || hipMalloc(&c->d_first_err, 256) != hipSuccess ||
+      hipHostMalloc(&c->h_poll, 64, hipHostMallocDefault) != hipSuccess ||
+      gmpk_clear_word(c->d_first_err, nullptr) != 0 || hipDeviceSynchronize() != hipSuccess) {
     gmp_ctx_destroy(c);
     return GMP_EDEVICE;
   }
@@ -160,8 +166,26 @@ extern "C" void gmp_ctx_destroy(gmp_ctx* c) {
   if (c->h_jobs) (void)hipHostFree(c->h_jobs);
   if (c->d_ws) (void)hipFree(c->d_ws);
   if (c->d_queue) (void)hipFree(c->d_queue);
+  if (c->d_first_err) (void)hipFree(c->d_first_err);
+  if (c->h_poll) (void)hipHostFree(c->h_poll);
   if (c->done) (void)hipEventDestroy(c->done);
   delete c;
+}
+
+int32_t* gmp_ctx_first_err_word(gmp_ctx* c) { return c ? c->d_first_err : nullptr; }
+int gmp_ctx_device(gmp_ctx* c) { return c ? c->device : 0; }
+
+extern "C" gmp_status gmp_poll(gmp_ctx* c, void* stream, int32_t* h_first_error) {
+  if (!c || !h_first_error) return GMP_EINVAL;
+  HIP_OK(hipSetDevice(c->device));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // the word is taken and cleared in one atomic exchange on the device, so an
+  // error recorded by a launch still running on another stream is not lost
+  if (gmpk_take_word(c->d_first_err, c->d_first_err + 1, s) != 0) return GMP_EDEVICE;
+  HIP_OK(hipMemcpyAsync(c->h_poll, c->d_first_err + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *h_first_error = *c->h_poll;
+  return GMP_OK;
 }
 
 namespace {
@@ -197,15 +221,17 @@ gmp_status ctx_launch(gmp_ctx* c, size_t n_jobs, uint32_t flags, hipStream_t s) 
   HIP_OK(hipMemcpyAsync(c->d_jobs, c->h_jobs, n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, s));
   // the single-block and single-stream calls use the workgroup shape the
   // benchmark times: seven decoder wavefronts (two per SIMD)
-  if (gmpk_launch(c->d_jobs, (uint32_t)n_jobs, flags, 7, 0, 0, c->d_queue, s) != 0) return GMP_EDEVICE;
+  if (gmpk_launch(c->d_jobs, (uint32_t)n_jobs, flags, 7, 0, 0, c->d_queue, c->d_first_err, s) != 0)
+    return GMP_EDEVICE;
   HIP_OK(hipEventRecord(c->done, s));
   c->pending = true;
   return GMP_OK;
 }
 
-bool valid_flags(uint32_t flags) {
-  return (flags & ~(GMP_MODE_MASK | GMP_FLAG_STATS)) == 0 && (flags & GMP_MODE_MASK) != 3u;
-}
+bool valid_flags(uint32_t flags) { return (flags & ~(GMP_MODE_MASK | GMP_FLAG_STATS | GMP_FLAG_VERIFY_DE)) == 0; }
+
+// Device blocks are read with 16-byte asynchronous copies into LDS.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 }  // namespace
 
@@ -213,7 +239,7 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
                                            size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status,
                                            uint32_t flags, void* stream) {
   if (!c || !d_block || !h_block || !d_status || !valid_flags(flags) || (flags & GMP_FLAG_STATS)) return GMP_EINVAL;
-  if (reinterpret_cast<uintptr_t>(d_block) & 3) return GMP_EINVAL;
+  if (!aligned16(d_block)) return GMP_EINVAL;
   gmp_block_info info;
   gmp_status st = gmp_block_info_parse(h_block, h_len, &info);
   if (st != GMP_OK) return st;
@@ -233,6 +259,8 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
   j.rounds = nullptr;
   j.times = nullptr;
   j.status = d_status;
+  j.stats = nullptr;
+  j.done = nullptr;
   j.n_seq = info.n_seq;
   j.n_lit = info.n_lit;
   return ctx_launch(c, 1, flags, static_cast<hipStream_t>(stream));
@@ -242,6 +270,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
                                             uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
                                             void* stream) {
   if (!c || !d_stream || !h_stream || !d_status || !valid_flags(flags) || (flags & GMP_FLAG_STATS)) return GMP_EINVAL;
+  if (!aligned16(d_stream)) return GMP_EINVAL;
   uint32_t nb = 0, bs = 0;
   uint64_t total = 0;
   gmp_status st = gmp_stream_info(h_stream, len, &nb, &bs, &total);
@@ -255,7 +284,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
   uint64_t ws_total = 0;
   for (uint32_t b = 0; b <= nb; b++) offs[b] = rd64(hs + 32 + 8 * (size_t)b);
   for (uint32_t b = 0; b < nb; b++) {
-    if (offs[b] > offs[b + 1] || offs[b + 1] > len || (offs[b] & 3)) return GMP_EFORMAT;
+    if (offs[b] > offs[b + 1] || offs[b + 1] > len || (offs[b] & 15)) return GMP_EFORMAT;
     if ((st = gmp_block_info_parse(hs + offs[b], offs[b + 1] - offs[b], &infos[b])) != GMP_OK) return st;
     if (infos[b].block_bytes > offs[b + 1] - offs[b]) return GMP_EFORMAT;
     const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
@@ -276,6 +305,8 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = d_status + b;
+    j.stats = nullptr;
+    j.done = nullptr;
     j.n_seq = infos[b].n_seq;
     j.n_lit = infos[b].n_lit;
     ws_off += j.ws_len;
@@ -292,7 +323,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
   uint64_t ws_total = 0;
   for (uint32_t i = 0; i < n_jobs; i++) {
     const gmp_job& j = h_jobs[i];
-    if (!j.d_comp || (reinterpret_cast<uintptr_t>(j.d_comp) & 3) || (!j.d_out && j.out_len)) return GMP_EINVAL;
+    if (!j.d_comp || !aligned16(j.d_comp) || (!j.d_out && j.out_len)) return GMP_EINVAL;
     ws_total += gmpk::workspace_bytes(j.n_seq, j.n_lit, j.comp_len);
   }
   gmp_batch* b = new (std::nothrow) gmp_batch();
@@ -300,6 +331,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
   b->device = c->device;
   b->n = n_jobs;
   b->num_cu = c->num_cu;
+  b->d_first_err = c->d_first_err;
   if (hipMalloc(&b->d_queue, 256) != hipSuccess || (n_jobs && hipMalloc(&b->d_jobs, n_jobs * sizeof(gmpk::DevJob)) != hipSuccess) ||
       (ws_total && hipMalloc(&b->d_ws, ws_total) != hipSuccess)) {
     gmp_batch_destroy(b);
@@ -325,6 +357,8 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     d.rounds = j.d_rounds;
     d.times = j.d_times;
     d.status = d_status + i;
+    d.stats = j.d_stats;
+    d.done = nullptr;
     d.n_seq = j.n_seq;
     d.n_lit = j.n_lit;
     ws_off += d.ws_len;
@@ -358,7 +392,7 @@ gmp_status launch_params(const gmp_batch* b, const gmp_tuning* tuning, Launch* l
 }
 
 gmp_status batch_launch(gmp_batch* b, uint32_t flags, const Launch& l, hipStream_t s) {
-  if (gmpk_launch(b->d_jobs, b->n, flags, l.waves, l.persistent, l.workgroups, b->d_queue, s) != 0)
+  if (gmpk_launch(b->d_jobs, b->n, flags, l.waves, l.persistent, l.workgroups, b->d_queue, b->d_first_err, s) != 0)
     return GMP_EDEVICE;
   return GMP_OK;
 }

@@ -6,14 +6,16 @@
 #define GMPK_MODE_AUTO 0u
 #define GMPK_MODE_MRR 1u
 #define GMPK_MODE_DE 2u
+#define GMPK_MODE_SC 3u
 #define GMPK_MODE_MASK 3u
 #define GMPK_FLAG_STATS 0x100u
+#define GMPK_FLAG_VERIFY_DE 0x200u
 
 namespace gmpk {
 
 constexpr int kMaxDecWaves = 7;  // decoder wavefronts per workgroup: 1, 2, 4 or 7
 
-// One block to decode (device copy of a host job, 80 bytes).
+// One block to decode (device copy of a host job, 96 bytes).
 struct DevJob {
   const uint8_t* comp;  // the block: header, index, payload
   uint64_t comp_len;
@@ -24,9 +26,19 @@ struct DevJob {
   uint8_t* rounds;      // optional per-group round counts
   uint64_t* times;      // optional phase timestamps (4 per block)
   int32_t* status;      // the block's status word
+  uint32_t* stats;      // optional kStatsWords counters (see below)
+  uint32_t* done;       // optional counter in host-visible memory: +1 when the block has finished
   uint32_t n_seq, n_lit;
 };
-static_assert(sizeof(DevJob) == 80, "DevJob layout");
+static_assert(sizeof(DevJob) == 96, "DevJob layout");
+
+// Per-block counters written with GMPK_FLAG_STATS when DevJob::stats is set:
+//   [0] how the sub-blocks were decoded: 1 segmented, 2 one lane per sub-block
+//   [1] decoder lanes whose start was repaired (segmented decoding)
+//   [2] groups of 64 sequences, [3] groups resolved in window-sized pieces
+//   [4] groups of a DE block resolved by rounds because they break the DE rule
+//   [16 + r] back-reference bytes copied in round r + 1 (r < 64), all groups
+constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 
 // Token workspace of one block: the final token stream (n_seq 8-byte records,
 // then n_lit literal bytes), then the private areas of the segmented decoder
@@ -58,5 +70,12 @@ __host__ __device__ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_l
 
 }  // namespace gmpk
 
+// d_first_err (may be null): set to the first non-zero block status of any launch
+// that names it, until the host clears it.
 extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t dec_waves,
-                           uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, hipStream_t stream);
+                           uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, int32_t* d_first_err,
+                           hipStream_t stream);
+// Small kernels of the host API (no memset nodes, so graph captures stay plain):
+// *word = 0; and *out = *word, *word = 0 in one atomic exchange.
+extern "C" int gmpk_clear_word(int32_t* word, hipStream_t stream);
+extern "C" int gmpk_take_word(int32_t* word, int32_t* out, hipStream_t stream);

@@ -219,6 +219,10 @@ struct Misc {
   uint32_t next_job;
   uint32_t abort;  // set when a wait exceeded its bound: every wavefront stops waiting
   int err;
+  // statistics (GMPK_FLAG_STATS with DevJob::stats): bytes copied per round,
+  // groups resolved in pieces, DE groups resolved by rounds
+  uint32_t rbytes[64];
+  uint32_t n_split, n_de_rounds, a2_path, n_repaired;
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
@@ -1208,12 +1212,19 @@ __device__ void coop_lits(uint32_t pos, uint32_t lsrc, uint32_t n, uint32_t* scr
 }
 
 // ---------------------------------------------------------------- A3-A6
+// How a group's back-references are resolved: Multi-Round Resolution, one
+// pass (Dependency Elimination streams), or Sequential Copying, the paper's
+// baseline in its comparison of resolution strategies (one back-reference
+// after another, in sequence order).
+constexpr uint32_t kResMRR = 0, kResDE = 1, kResSC = 2;
 struct LzArgs {
   const GMEM uint8_t* ws;  // token workspace: records, then literal bytes
   uint64_t ws_len;
   GMEM uint8_t* out;
   uint32_t n_seq, n_lit, raw_len;
-  bool single_pass;
+  uint32_t res;      // kResMRR, kResDE (one pass) or kResSC (one back-reference at a time)
+  bool verify_de;    // a DE group that breaks the DE rule is an error (it is resolved by rounds either way)
+  bool stats;        // count bytes per round, split groups and DE groups resolved by rounds
   GMEM uint8_t* rounds;
   // After segmented decoding the records are read from the lane areas
   // (priv: the first area; null: from the packed stream in ws)
@@ -1434,12 +1445,13 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
     const uint32_t tot_lit = readlane(inc_lit, 63);
     uint32_t lsrc = g_lit + inc_lit - L;
     uint32_t pos = g_out + inc_out - (L + M0);
-    const uint32_t end = pos + L + M0;
     // a distance reaching before the block's start is an error (EDIST); such
     // a copy is dropped so that resolution still ends
     const bool bad_dist = valid && M0 > 0 && D > pos + L;
     if (__ballot(bad_dist)) set_err(kEDIST);
     const uint32_t M = bad_dist ? 0u : M0;
+    // end of the bytes the lane writes (a dropped copy writes none)
+    const uint32_t end = pos + L + M;
     const uint32_t m_cnt = min(64u, a.n_seq - g0);
     const uint32_t g_end = g_out + readlane(inc_out, 63);
     // literals come from the LDS ring unless the group holds more than half of it
@@ -1449,6 +1461,25 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       break;
     uint32_t rounds = 0;
     bool split = false;
+    // A DE block's group is resolved in one pass only if it keeps the rule its
+    // compressor promised: every source ends at or before the destination of
+    // the group's first back-reference (the group's frozen high-water mark).
+    // A group that breaks it is resolved by rounds, which gives the sequential
+    // result; with verify_de it is moreover an error (EDIST, the class the
+    // format check gives a DE block that breaks the rule).
+    bool one_pass = a.res == kResDE;
+    if (one_pass) {
+      const uint32_t dst0 = pos + L;
+      const uint64_t mv = __ballot(valid && M > 0);
+      if (mv) {
+        const uint32_t hwm = readlane(dst0, (uint32_t)__builtin_ctzll(mv));
+        if (__ballot(valid && M > 0 && dst0 - D + M > hwm)) {
+          if (a.verify_de) set_err(kEDIST);
+          if (a.stats && lane == 0) atomicAdd(&s_misc.n_de_rounds, 1u);
+          one_pass = false;
+        }
+      }
+    }
     // fast path: the group's literals are staged and its output fits the
     // window; "plain" when moreover no copy wraps around the ring or the
     // literal ring and none overlaps its own output (most groups)
@@ -1486,8 +1517,13 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // then run round after round (a wavefront's LDS accesses stay in order,
       // so each round reads what the earlier ones wrote).
       uint32_t my_round = has ? 1u : 0u;
-      if (a.single_pass) {
+      if (one_pass) {
         rounds = __ballot(has) ? 1u : 0u;
+      } else if (a.res == kResSC) {
+        // one back-reference per round, in sequence order
+        const uint64_t hv = __ballot(has);
+        my_round = has ? 1u + (uint32_t)__popcll(hv & ((1ull << lane) - 1ull)) : 0u;
+        rounds = (uint32_t)__popcll(hv);
       } else {
         bool pending = has;
         for (;;) {
@@ -1522,6 +1558,12 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // its output is final once everything in front of it is
       if (!wait_done(g_out)) break;
       lds_release(&s_misc.done_upto, g_end);
+      if (a.stats) {
+        for (uint32_t r = 1; r <= rounds && r <= 64; r++) {
+          const uint32_t b = readlane(wave_incl_scan(my_round == r ? M : 0u), 63);
+          if (lane == 0) atomicAdd(&s_misc.rbytes[r - 1], b);
+        }
+      }
     } else {
       // general path, after every earlier group is final: the group is
       // resolved in pieces that fit the window, a literal run longer than the
@@ -1554,6 +1596,14 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
         }
         const uint64_t fit = __ballot(valid && lane >= lo && end - base <= kSpanCap);
         const uint32_t hi = lo + (uint32_t)__popcll(fit);
+        if (hi == lo) {
+          // lane lo's literals were cut down to at most kSpanCap above and its
+          // copy is at most 258 bytes, so it always fits; this guards the loop
+          // against an inconsistent state, which ends the block with an error
+          set_err(kEFORMAT);
+          ok = false;
+          break;
+        }
         if (hi < m_cnt) split = true;
         const bool active = lane >= lo && lane < hi;
         const uint32_t piece_end = readlane(end, hi - 1);
@@ -1571,10 +1621,24 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
         }
         const uint32_t dst = pos + L;
         bool pending = active && M > 0;
-        if (a.single_pass) {
+        if (one_pass) {
           // A6: no back-reference of the group depends on another (DE)
-          if (__ballot(pending)) rounds += 1;
+          if (__ballot(pending)) {
+            rounds += 1;
+            if (a.stats) {
+              const uint32_t b = readlane(wave_incl_scan(pending ? M : 0u), 63);
+              if (lane == 0) atomicAdd(&s_misc.rbytes[0], b);
+            }
+          }
           if (pending) copy_match(ring, dst, M, D);
+        } else if (a.res == kResSC) {
+          // Sequential Copying: one back-reference at a time, in order
+          for (uint64_t votes = __ballot(pending); votes; votes &= votes - 1) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(votes);
+            if (lane == l) copy_match(ring, dst, M, D);
+            if (a.stats && lane == 0 && rounds < 64) atomicAdd(&s_misc.rbytes[rounds], readlane(M, l));
+            rounds++;
+          }
         } else {
           // A5: Multi-Round Resolution
           const uint32_t need_end = dst - D + min(M, D);
@@ -1582,9 +1646,14 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
             const uint64_t votes = __ballot(pending);
             if (votes == 0) break;
             const uint32_t hwm = readlane(dst, (uint32_t)__builtin_ctzll(votes));
-            if (pending && need_end <= hwm) {
+            const bool can = pending && need_end <= hwm;
+            if (can) {
               copy_match(ring, dst, M, D);
               pending = false;
+            }
+            if (a.stats) {
+              const uint32_t b = readlane(wave_incl_scan(can ? M : 0u), 63);
+              if (lane == 0 && rounds < 64) atomicAdd(&s_misc.rbytes[rounds], b);
             }
             rounds++;
           }
@@ -1593,9 +1662,13 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
         lo = hi;
       }
       if (!ok) break;
+      // a dropped copy (bad distance) leaves its bytes unwritten: the group's
+      // output still ends at g_end, so the next group's wait ends
+      lds_release(&s_misc.done_upto, g_end);
       lds_release(&s_misc.next_group[w], g + kRes);
     }
     if (a.rounds && lane == 0) a.rounds[g] = (uint8_t)(min(rounds, 127u) | (split ? 0x80u : 0u));
+    if (a.stats && split && lane == 0) atomicAdd(&s_misc.n_split, 1u);
   }
   lds_release(&s_misc.next_group[w], kDone);
 }
@@ -1853,9 +1926,11 @@ __device__ __forceinline__ void stamp(const DevJob& job, int i) {
   if (job.times && threadIdx.x == 0) gmem(job.times)[i] = wall_clock64();
 }
 
-// kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR or GMPK_MODE_DE.
+// Decodes one block and returns its status (the same value in every thread).
+// kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR,
+// GMPK_MODE_DE or GMPK_MODE_SC.
 template <int kDec, int kMode>
-__device__ void inflate_block(const DevJob& job, uint32_t flags) {
+__device__ int inflate_block(const DevJob& job, uint32_t flags) {
   constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
@@ -1863,10 +1938,14 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   if (t == 0) {
     sh.err = 0;
     sh.abort = 0;
+    sh.n_split = 0;
+    sh.n_de_rounds = 0;
+    sh.a2_path = 0;
+    sh.n_repaired = 0;
   }
+  if (t < 64) sh.rbytes[t] = 0;
   __syncthreads();
   const GMEM uint8_t* blk = gmem(job.comp);
-  GMEM int32_t* status = gmem(job.status);
   // ---- A0: header
   int err = kOK;
   uint32_t mode = 0, group = 0, lmax = 0, raw_len = 0, window = 0, max_match = 0, n_sub = 0, n_seq = 0,
@@ -1903,14 +1982,10 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   const bool de_ok = mode == 1 && (group % 64) == 0;
   if (err == kOK && kMode == GMPK_MODE_DE && !de_ok) err = kEINVAL;
   const bool single_pass = (kMode == GMPK_MODE_DE) || (kMode == GMPK_MODE_AUTO && de_ok);
-  if (err != kOK) {
-    if (t == 0) *status = err;
-    return;
-  }
+  if (err != kOK) return err;
   if (n_sub == 0) {
     // an empty block: nothing to decode
-    if (t == 0) *status = (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kOK : kEFORMAT;
-    return;
+    return (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kOK : kEFORMAT;
   }
   // ---- A1: code lengths and lookup tables
   for (uint32_t i = t; i < kNumLL + kNumD; i += kThreads) sh.lens[i] = (blk[32 + i / 2] >> ((i & 1) * 4)) & 15;
@@ -1922,10 +1997,7 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   __syncthreads();
   build_table<kThreads>(sh.lens + kNumLL, kNumD, lmax, lut_d, true);
   __syncthreads();
-  if (sh.err) {
-    if (t == 0) *status = sh.err;
-    return;
-  }
+  if (sh.err) return sh.err;
   stamp(job, 1);
   // ---- A0/A2: sub-block offsets by prefix sums over the index, then decode
   const GMEM uint8_t* idx = blk + kHdrBytes;
@@ -1987,11 +2059,10 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   if (!segmented && t == 0 &&
       (carry[0] * 4ull != payload || carry[1] != n_seq || carry[2] != n_lit || carry[3] != raw_len))
     set_err(kEFORMAT);
+  if (t == 0) sh.a2_path = segmented ? 1u : 2u;
+  if (segmented && t < kLanes && (s_seg.flags[t] & kSegRep)) atomicAdd(&sh.n_repaired, 1u);
   __syncthreads();  // workspace writes of all lanes are visible after this barrier
-  if (sh.err || sh.abort) {
-    if (t == 0) *status = sh.abort ? kESTALL : sh.err;
-    return;
-  }
+  if (sh.err || sh.abort) return sh.abort ? kESTALL : sh.err;
   stamp(job, 2);
   // ---- A3-A6: the decoder wavefronts resolve, the fetcher stages tokens,
   // the last wavefront writes the output
@@ -2002,7 +2073,9 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   a.n_seq = n_seq;
   a.n_lit = n_lit;
   a.raw_len = raw_len;
-  a.single_pass = single_pass;
+  a.res = kMode == GMPK_MODE_SC ? kResSC : (single_pass ? kResDE : kResMRR);
+  a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
+  a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
   a.priv = nullptr;
   if (segmented) {
@@ -2030,16 +2103,47 @@ __device__ void inflate_block(const DevJob& job, uint32_t flags) {
   }
   __syncthreads();
   stamp(job, 3);
-  if (t == 0) *status = sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
+  return sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
+}
+
+// One block from start to end: decode, then its status word, the first-error
+// word, its statistics and its completion counter.
+template <int kDec, int kMode>
+__device__ void run_block(const DevJob& job, uint32_t flags, int32_t* first_err) {
+  const int st = inflate_block<kDec, kMode>(job, flags);
+  const uint32_t t = threadIdx.x;
+  __syncthreads();
+  if (t == 0) {
+    *gmem(job.status) = st;
+    if (st != kOK && first_err) atomicCAS(first_err, 0, st);
+  }
+  if ((flags & GMPK_FLAG_STATS) && job.stats) {
+    GMEM uint32_t* o = gmem(job.stats);
+    if (t < 64) o[kStatsRoundBytes + t] = s_misc.rbytes[t];
+    if (t == 0) {
+      o[0] = s_misc.a2_path;
+      o[1] = s_misc.n_repaired;
+      o[2] = (job.n_seq + 63) / 64;
+      o[3] = s_misc.n_split;
+      o[4] = s_misc.n_de_rounds;
+    }
+  }
+  if (job.done) {
+    // every thread's output stores are made visible beyond the device before
+    // the block announces itself finished
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) __hip_atomic_fetch_add(job.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 template <int kDec, int kMode>
 __global__ __launch_bounds__(block_threads<kDec>()) void inflate_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
-                                                                  uint32_t flags) {
+                                                                  uint32_t flags, int32_t* first_err) {
   if (blockIdx.x >= n_jobs) return;
   DevJob job = jobs[blockIdx.x];
   if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
-  inflate_block<kDec, kMode>(job, flags);
+  run_block<kDec, kMode>(job, flags, first_err);
 }
 
 // Persistent form: workgroups take block indices from a device counter until
@@ -2048,7 +2152,8 @@ __global__ __launch_bounds__(block_threads<kDec>()) void inflate_kernel(const De
 template <int kDec, int kMode>
 __global__ __launch_bounds__(block_threads<kDec>()) void inflate_persistent_kernel(const DevJob* __restrict__ jobs,
                                                                              uint32_t n_jobs, uint32_t flags,
-                                                                             uint32_t* __restrict__ queue) {
+                                                                             uint32_t* __restrict__ queue,
+                                                                             int32_t* first_err) {
   for (;;) {
     if (threadIdx.x == 0) s_misc.next_job = atomicAdd(queue, 1u);
     __syncthreads();
@@ -2057,7 +2162,7 @@ __global__ __launch_bounds__(block_threads<kDec>()) void inflate_persistent_kern
     if (j >= n_jobs) return;
     DevJob job = jobs[j];
     if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
-    inflate_block<kDec, kMode>(job, flags);
+    run_block<kDec, kMode>(job, flags, first_err);
     __syncthreads();
   }
 }
@@ -2067,43 +2172,66 @@ __global__ void reset_queue_kernel(uint32_t* queue) { *queue = 0; }
 
 template <int kDec, int kMode>
 void launch_one(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t persistent, uint32_t workgroups,
-                uint32_t* d_queue, hipStream_t stream) {
+                uint32_t* d_queue, int32_t* first_err, hipStream_t stream) {
   if (persistent) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, d_queue);
-    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(block_threads<kDec>()), 0, stream,
-                       d_jobs, n_jobs, flags, d_queue);
+    hipLaunchKernelGGL((inflate_persistent_kernel<kDec, kMode>), dim3(workgroups), dim3(block_threads<kDec>()), 0,
+                       stream, d_jobs, n_jobs, flags, d_queue, first_err);
   } else {
-    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(block_threads<kDec>()), 0, stream, d_jobs, n_jobs,
-                       flags);
+    hipLaunchKernelGGL((inflate_kernel<kDec, kMode>), dim3(n_jobs), dim3(block_threads<kDec>()), 0, stream, d_jobs,
+                       n_jobs, flags, first_err);
   }
 }
 
 template <int kDec>
 int launch_mode(const DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t persistent, uint32_t workgroups,
-                uint32_t* d_queue, hipStream_t stream) {
+                uint32_t* d_queue, int32_t* first_err, hipStream_t stream) {
   switch (flags & GMPK_MODE_MASK) {
-    case GMPK_MODE_AUTO: launch_one<kDec, GMPK_MODE_AUTO>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
-    case GMPK_MODE_MRR: launch_one<kDec, GMPK_MODE_MRR>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
-    case GMPK_MODE_DE: launch_one<kDec, GMPK_MODE_DE>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); return 0;
-    default: return -1;
+    case GMPK_MODE_AUTO:
+      launch_one<kDec, GMPK_MODE_AUTO>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, first_err, stream);
+      return 0;
+    case GMPK_MODE_MRR:
+      launch_one<kDec, GMPK_MODE_MRR>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, first_err, stream);
+      return 0;
+    case GMPK_MODE_DE:
+      launch_one<kDec, GMPK_MODE_DE>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, first_err, stream);
+      return 0;
+    default:
+      launch_one<kDec, GMPK_MODE_SC>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, first_err, stream);
+      return 0;
   }
 }
 
 }  // namespace gmpk
 
 extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t flags, uint32_t dec_waves,
-                           uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, hipStream_t stream) {
+                           uint32_t persistent, uint32_t workgroups, uint32_t* d_queue, int32_t* d_first_err,
+                           hipStream_t stream) {
   using namespace gmpk;
   if (n_jobs == 0) return 0;
-  if (persistent && workgroups == 0) return -1;
+  if (persistent && (workgroups == 0 || !d_queue)) return -1;
   int rc;
   switch (dec_waves) {
-    case 1: rc = launch_mode<1>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 2: rc = launch_mode<2>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 4: rc = launch_mode<4>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
-    case 7: rc = launch_mode<7>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, stream); break;
+    case 1: rc = launch_mode<1>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, d_first_err, stream); break;
+    case 2: rc = launch_mode<2>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, d_first_err, stream); break;
+    case 4: rc = launch_mode<4>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, d_first_err, stream); break;
+    case 7: rc = launch_mode<7>(d_jobs, n_jobs, flags, persistent, workgroups, d_queue, d_first_err, stream); break;
     default: return -1;
   }
   if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? 0 : -8;
+}
+
+namespace gmpk {
+__global__ void clear_word_kernel(int32_t* word) { *word = 0; }
+__global__ void take_word_kernel(int32_t* word, int32_t* out) { *out = atomicExch(word, 0); }
+}  // namespace gmpk
+
+extern "C" int gmpk_clear_word(int32_t* word, hipStream_t stream) {
+  hipLaunchKernelGGL(gmpk::clear_word_kernel, dim3(1), dim3(1), 0, stream, word);
+  return hipGetLastError() == hipSuccess ? 0 : -8;
+}
+extern "C" int gmpk_take_word(int32_t* word, int32_t* out, hipStream_t stream) {
+  hipLaunchKernelGGL(gmpk::take_word_kernel, dim3(1), dim3(1), 0, stream, word, out);
   return hipGetLastError() == hipSuccess ? 0 : -8;
 }

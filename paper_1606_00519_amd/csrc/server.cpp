@@ -6,12 +6,14 @@
 // flight (compressed + decompressed + token workspace) stay within the
 // budget, and whenever one of its launch slots is free it launches every
 // admitted request not yet running as ONE kernel over all their blocks
-// (largest blocks first), on that slot's stream.  Requests that arrive while
-// others run join the next launch; launches of different slots overlap on
-// the device.  (One launch per request would leave the device mostly idle:
-// a request has only a handful of blocks, and the runtime runs few kernels
-// at once.)  When a launch completes, its requests' budget and workspace are
-// released and more are admitted.
+// (largest blocks first; one kernel per flag set), on that slot's stream.
+// Requests that arrive while others run join the next launch; launches of
+// different slots overlap on the device.  (One launch per request would
+// leave the device mostly idle: a request has only a handful of blocks, and
+// the runtime runs few kernels at once.)  Each block adds one to its
+// request's completion counter in host-visible memory when it has finished,
+// so a request completes, and its budget and workspace return, as soon as
+// its own blocks are done, not when its launch ends.
 //
 // Token workspace comes from one device arena owned by the server, handed
 // out first-fit in 256-byte units; everything else (compressed input,
@@ -31,6 +33,7 @@
 #include <vector>
 
 #include "../../include/gompresso.h"
+#include "host_internal.h"
 #include "inflate.h"
 
 namespace {
@@ -97,8 +100,10 @@ class Arena {
 
 struct Request {
   gmp_request r;
-  std::vector<gmpk::DevJob> jobs;  // device pointers filled in at submission, except ws
-  uint64_t ws_bytes = 0, bytes = 0, t_submit = 0, ws_off = 0;
+  std::vector<gmpk::DevJob> jobs;  // device pointers filled in at submission, except ws and done
+  uint64_t ws_bytes = 0, bytes = 0, t_submit = 0, t_launch = 0, ws_off = 0;
+  uint32_t ctr = 0;    // its completion counter (host-visible memory)
+  bool finished = false;
 };
 
 struct Slot {
@@ -108,18 +113,25 @@ struct Slot {
   gmpk::DevJob* h_jobs = nullptr;  // pinned
   size_t cap = 0;
   bool busy = false;
-  std::vector<Request> reqs;  // requests of the running launch
-  uint64_t t_launch = 0;
+  std::vector<Request> reqs;  // requests of the running launch(es)
 };
 
 }  // namespace
 
 struct gmp_server {
   int device = 0;
-  uint64_t budget = 0;
+  uint64_t budget = 0, arena_bytes = 0;
   gmp_tuning tuning{};
+  int32_t* d_first_err = nullptr;  // the context's first-error word
   uint8_t* d_arena = nullptr;
   Arena* arena = nullptr;
+  // Completion counters, one per request in flight, in pinned host memory that
+  // the kernels update: each block adds one when it has finished, so the
+  // scheduler sees a request complete as soon as its last block is done,
+  // while other requests of the same launch still run.
+  uint32_t* h_done = nullptr;
+  uint32_t* d_done = nullptr;  // the same memory, as the device sees it
+  std::vector<uint32_t> free_ctr;
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv;
@@ -135,19 +147,27 @@ struct gmp_server {
 
 namespace {
 
-void complete(gmp_server* s, const Request& rq, int32_t status, uint64_t t_launch) {
+constexpr uint32_t kCounters = 4096;  // most requests admitted at once
+
+// A request leaves the server: completion record, budget, workspace and counter back.
+void retire(gmp_server* s, Request& rq, int32_t status) {
   gmp_completion c{};
   c.tag = rq.r.tag;
   c.status = status;
   c.t_submit_ns = rq.t_submit;
-  c.t_admit_ns = t_launch;
+  c.t_admit_ns = rq.t_launch;
   c.t_done_ns = now_ns();
   c.bytes = rq.r.out_len;
   s->completed.push_back(c);
   s->finished++;
+  if (rq.ws_bytes) s->arena->release(rq.ws_off, rq.ws_bytes);
+  s->in_flight_bytes -= rq.bytes;
+  s->free_ctr.push_back(rq.ctr);
+  rq.finished = true;
 }
 
-// Launch every ready request as one kernel on slot `sl`.
+// Launch every ready request on slot `sl`: one kernel per distinct flag set
+// (resolution mode, DE check) over all the blocks of the requests that use it.
 gmp_status launch_ready(gmp_server* s, Slot& sl) {
   size_t n = 0;
   for (const Request& rq : s->ready) n += rq.jobs.size();
@@ -163,24 +183,33 @@ gmp_status launch_ready(gmp_server* s, Slot& sl) {
       return GMP_ENOMEM;
     sl.cap = cap;
   }
+  std::vector<uint32_t> flag_sets;
+  for (const Request& rq : s->ready)
+    if (std::find(flag_sets.begin(), flag_sets.end(), rq.r.flags) == flag_sets.end()) flag_sets.push_back(rq.r.flags);
   size_t k = 0;
-  for (const Request& rq : s->ready) {
-    uint64_t o = rq.ws_off;
-    for (const gmpk::DevJob& j : rq.jobs) {
-      sl.h_jobs[k] = j;
-      sl.h_jobs[k].ws = s->d_arena + o;
-      o += j.ws_len;
-      k++;
+  for (uint32_t f : flag_sets) {
+    const size_t k0 = k;
+    for (const Request& rq : s->ready) {
+      if (rq.r.flags != f) continue;
+      uint64_t o = rq.ws_off;
+      for (const gmpk::DevJob& j : rq.jobs) {
+        sl.h_jobs[k] = j;
+        sl.h_jobs[k].ws = s->d_arena + o;
+        sl.h_jobs[k].done = s->d_done + rq.ctr;
+        o += j.ws_len;
+        k++;
+      }
     }
-  }
-  // largest blocks first, so the long ones start early
-  std::stable_sort(sl.h_jobs, sl.h_jobs + n,
-                   [](const gmpk::DevJob& x, const gmpk::DevJob& y) { return x.out_len > y.out_len; });
-  if (n) {
-    if (hipMemcpyAsync(sl.d_jobs, sl.h_jobs, n * sizeof(gmpk::DevJob), hipMemcpyHostToDevice, sl.stream) !=
-            hipSuccess ||
-        gmpk_launch(sl.d_jobs, (uint32_t)n, GMP_MODE_AUTO, s->tuning.waves_per_block, 0, 0, nullptr, sl.stream) != 0)
-      return GMP_EDEVICE;
+    // largest blocks first, so the long ones start early
+    std::stable_sort(sl.h_jobs + k0, sl.h_jobs + k,
+                     [](const gmpk::DevJob& x, const gmpk::DevJob& y) { return x.out_len > y.out_len; });
+    if (k > k0) {
+      if (hipMemcpyAsync(sl.d_jobs + k0, sl.h_jobs + k0, (k - k0) * sizeof(gmpk::DevJob), hipMemcpyHostToDevice,
+                         sl.stream) != hipSuccess ||
+          gmpk_launch(sl.d_jobs + k0, (uint32_t)(k - k0), f, s->tuning.waves_per_block, 0, 0, nullptr,
+                      s->d_first_err, sl.stream) != 0)
+        return GMP_EDEVICE;
+    }
   }
   if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return GMP_EDEVICE;
   return GMP_OK;
@@ -192,33 +221,45 @@ void serve(gmp_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop.load()) {
     bool progress = false;
-    // completed launches: their requests finish, budget and workspace return
+    // requests whose blocks have all finished, and launches that completed
     for (Slot& sl : s->slots) {
       if (!sl.busy) continue;
+      for (Request& rq : sl.reqs) {
+        if (rq.finished) continue;
+        const uint32_t d = __atomic_load_n(&s->h_done[rq.ctr], __ATOMIC_ACQUIRE);
+        if (d >= rq.jobs.size()) {
+          retire(s, rq, GMP_OK);
+          progress = true;
+        }
+      }
       const hipError_t q = hipEventQuery(sl.done);
       if (q == hipErrorNotReady) continue;
-      for (const Request& rq : sl.reqs) {
-        complete(s, rq, q == hipSuccess ? GMP_OK : GMP_EDEVICE, sl.t_launch);
-        if (rq.ws_bytes) s->arena->release(rq.ws_off, rq.ws_bytes);
-        s->in_flight_bytes -= rq.bytes;
+      // the launch is over: a request still unfinished here was ended by a HIP error
+      for (Request& rq : sl.reqs) {
+        if (rq.finished) continue;
+        const uint32_t d = __atomic_load_n(&s->h_done[rq.ctr], __ATOMIC_ACQUIRE);
+        retire(s, rq, (q == hipSuccess && d >= rq.jobs.size()) ? GMP_OK : GMP_EDEVICE);
+        if (q != hipSuccess && s->error == GMP_OK) s->error = GMP_EDEVICE;
       }
-      if (q != hipSuccess && s->error == GMP_OK) s->error = GMP_EDEVICE;
       sl.reqs.clear();
       sl.busy = false;
       progress = true;
     }
-    // admissions, first come first served, within the budget and the arena
-    while (!s->pending.empty()) {
+    // admissions, first come first served, within the budget, the arena and the counters
+    while (!s->pending.empty() && !s->free_ctr.empty()) {
       Request& rq = s->pending.front();
       if (s->in_flight_bytes + rq.bytes > s->budget) break;
       if (rq.ws_bytes && !s->arena->alloc(rq.ws_bytes, &rq.ws_off)) break;
+      rq.ctr = s->free_ctr.back();
+      s->free_ctr.pop_back();
+      s->h_done[rq.ctr] = 0;
       s->in_flight_bytes += rq.bytes;
       if (s->in_flight_bytes > s->peak_bytes) s->peak_bytes = s->in_flight_bytes;
       s->ready.push_back(std::move(rq));
       s->pending.pop_front();
       progress = true;
     }
-    // one launch for everything admitted, on a free slot
+    // one launch (per flag set) for everything admitted, on a free slot
     if (!s->ready.empty()) {
       Slot* free_slot = nullptr;
       uint32_t busy = 0;
@@ -229,18 +270,21 @@ void serve(gmp_server* s) {
       if (free_slot) {
         Slot& sl = *free_slot;
         const gmp_status st = launch_ready(s, sl);
-        sl.t_launch = now_ns();
+        const uint64_t t = now_ns();
+        for (Request& rq : s->ready) rq.t_launch = t;
         if (st != GMP_OK) {
-          for (const Request& rq : s->ready) {
-            complete(s, rq, st, sl.t_launch);
-            if (rq.ws_bytes) s->arena->release(rq.ws_off, rq.ws_bytes);
-            s->in_flight_bytes -= rq.bytes;
-          }
+          // kernels of other flag sets may have started: let them end before
+          // their requests' counters and workspace are handed out again
+          (void)hipStreamSynchronize(sl.stream);
+          for (Request& rq : s->ready) retire(s, rq, st);
           s->ready.clear();
           if (s->error == GMP_OK) s->error = st;
         } else {
           sl.reqs = std::move(s->ready);
           s->ready.clear();
+          // requests without blocks are complete at once
+          for (Request& rq : sl.reqs)
+            if (rq.jobs.empty()) retire(s, rq, GMP_OK);
           sl.busy = true;
           if (++busy > s->peak_slots) s->peak_slots = busy;
           s->launches++;
@@ -252,7 +296,7 @@ void serve(gmp_server* s) {
       s->cv.notify_all();
       continue;
     }
-    // nothing to do right now: wait for a submission, or poll the device again shortly
+    // nothing to do right now: wait for a submission, or look at the device again shortly
     bool any_busy = false;
     for (Slot& sl : s->slots) any_busy |= sl.busy;
     if (any_busy)
@@ -274,18 +318,26 @@ extern "C" gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uin
   if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4 && t.waves_per_block != 7)
     return GMP_EINVAL;
   if (t.persistent) return GMP_EINVAL;  // requests launch one workgroup per block
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return GMP_EDEVICE;
+  const int dev = gmp_ctx_device(ctx);
+  if (hipSetDevice(dev) != hipSuccess) return GMP_EDEVICE;
   gmp_server* s = new (std::nothrow) gmp_server();
   if (!s) return GMP_ENOMEM;
   s->device = dev;
   s->budget = budget_bytes;
   s->tuning = t;
+  s->d_first_err = gmp_ctx_first_err_word(ctx);
   if (workspace_bytes == 0) workspace_bytes = budget_bytes / 2;
   workspace_bytes = (workspace_bytes + kUnit - 1) / kUnit * kUnit;
+  s->arena_bytes = workspace_bytes;
   s->arena = new (std::nothrow) Arena(workspace_bytes);
   s->slots.resize(n_slots);
-  bool ok = s->arena && hipMalloc(&s->d_arena, workspace_bytes) == hipSuccess;
+  bool ok = s->arena && hipMalloc(&s->d_arena, workspace_bytes) == hipSuccess &&
+            hipHostMalloc(&s->h_done, kCounters * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess &&
+            hipHostGetDevicePointer((void**)&s->d_done, s->h_done, 0) == hipSuccess;
+  if (ok) {
+    for (uint32_t i = 0; i < kCounters; i++) s->h_done[i] = 0;
+    for (uint32_t i = kCounters; i-- > 0;) s->free_ctr.push_back(i);
+  }
   for (Slot& sl : s->slots) {
     ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
@@ -302,7 +354,8 @@ extern "C" gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uin
 extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
   if (!s || !req || !req->d_stream || !req->h_stream || !req->d_status) return GMP_EINVAL;
   const uint32_t mode = req->flags & GMP_MODE_MASK;
-  if ((req->flags & ~GMP_MODE_MASK) != 0 || mode == 3u) return GMP_EINVAL;
+  if ((req->flags & ~(GMP_MODE_MASK | GMP_FLAG_VERIFY_DE)) != 0) return GMP_EINVAL;
+  if (reinterpret_cast<uintptr_t>(req->d_stream) & 15) return GMP_EINVAL;
   const uint8_t* hs = static_cast<const uint8_t*>(req->h_stream);
   if (req->len < 32 || rd32(hs) != kMagicStream) return GMP_EFORMAT;
   const uint32_t bs = rd32(hs + 8), nb = rd32(hs + 12);
@@ -334,12 +387,15 @@ extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = req->d_status + b;
+    j.stats = nullptr;
+    j.done = nullptr;
     j.n_seq = info.n_seq;
     j.n_lit = info.n_lit;
     rq.ws_bytes += j.ws_len;
   }
   rq.bytes = req->len + req->out_len + rq.ws_bytes;
-  if (rq.bytes > s->budget) return GMP_EBUSY;  // could never be admitted
+  // could never be admitted: more bytes than the budget, or more workspace than the arena
+  if (rq.bytes > s->budget || rq.ws_bytes > s->arena_bytes) return GMP_EBUSY;
   rq.t_submit = now_ns();
   {
     std::lock_guard<std::mutex> g(s->mu);
@@ -414,6 +470,7 @@ extern "C" void gmp_server_destroy(gmp_server* s) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   if (s->d_arena) (void)hipFree(s->d_arena);
+  if (s->h_done) (void)hipHostFree(s->h_done);
   delete s->arena;
   delete s;
 }

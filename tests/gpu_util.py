@@ -51,9 +51,10 @@ def decode_block(ctx, blk: bytes, out_len: int, flags: int = 0):
 
 
 def decode_batch(ctx, blocks: list[bytes], flags: int = 0, waves: int = 1, persistent: bool = False,
-                 workgroups: int = 0, stats: bool = False, runs: int = 1):
+                 workgroups: int = 0, stats: bool = False, runs: int = 1, counters: list | None = None):
     """Decode independent blocks with one batch (gmp_batch_create / gmp_batch_run).
-    Returns (status array, list of outputs, list of per-group round arrays or None)."""
+    Returns (status array, list of outputs, list of per-group round arrays or None).
+    With stats and a `counters` list, each block's GMP_STATS_WORDS counters are appended to it."""
     import paper_1606_00519_amd as gmp
     torch = _torch()
     infos = [gmp.block_info(b) for b in blocks]
@@ -73,11 +74,13 @@ def decode_batch(ctx, blocks: list[bytes], flags: int = 0, waves: int = 1, persi
     ng = [(i["n_seq"] + 63) // 64 for i in infos]
     goff = np.concatenate([[0], np.cumsum(ng)]).astype(np.int64)
     rounds = torch.zeros((max(int(goff[-1]), 1),), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros((max(len(blocks), 1), gmp.STATS_WORDS), dtype=torch.int32, device="cuda")
     status = torch.full((max(len(blocks), 1),), 12345, dtype=torch.int32, device="cuda")
     jobs = []
     for k, (b, i) in enumerate(zip(blocks, infos)):
         jobs.append(gmp.Job(d_in.data_ptr() + offs[k], len(b), buf.data_ptr() + GUARD + outs[k], i["raw_len"],
-                            i["n_seq"], i["n_lit"], rounds.data_ptr() + int(goff[k]) if stats else None))
+                            i["n_seq"], i["n_lit"], rounds.data_ptr() + int(goff[k]) if stats else None, None,
+                            cnt.data_ptr() + 4 * gmp.STATS_WORDS * k if stats else None))
     print(f"[gpu] decode_batch blocks={len(blocks)} flags={flags:#x} waves={waves} persistent={persistent}",
           flush=True)
     batch = ctx.batch_create(jobs, status)
@@ -97,6 +100,9 @@ def decode_batch(ctx, blocks: list[bytes], flags: int = 0, waves: int = 1, persi
     assert np.all(o[prev_end:] == CANARY)
     r = rounds.cpu().numpy()
     rr = [r[goff[k]:goff[k + 1]].copy() for k in range(len(blocks))] if stats else None
+    if stats and counters is not None:
+        c = cnt.cpu().numpy().astype(np.int64)
+        counters.extend(c[k].copy() for k in range(len(blocks)))
     return status.cpu().numpy()[:len(blocks)], res, rr
 
 

@@ -128,3 +128,80 @@ def test_oversized_request_refused(ctx):
         srv.submit(r.d_in, r.stream, r.out, r.status)
     assert e.value.status == gmp.EBUSY
     srv.close()
+
+
+def test_request_larger_than_default_arena_refused(ctx):
+    # the budget admits the request's bytes, but its token workspace exceeds the
+    # default arena (half the budget): refused at submission, never queued
+    import paper_1606_00519_amd as gmp
+    raw, s = make_requests(n=1, hi=2 << 20, seed=24)[0]
+    r = Resident(raw, s)
+    ws = 0
+    for blk, _ in oracle.stream_blocks(s)[0]:
+        i = gmp.block_info(blk)
+        ws += gmp.workspace_bytes(i["n_seq"], i["n_lit"], len(blk))
+    total = len(s) + len(raw) + ws
+    budget = total + 1024
+    assert ws > budget // 2
+    srv = gmp.Server(ctx, budget_bytes=budget, slots=2)
+    with pytest.raises(gmp.GmpError) as e:
+        srv.submit(r.d_in, r.stream, r.out, r.status)
+    assert e.value.status == gmp.EBUSY
+    srv.drain(1000)
+    srv.close()
+
+
+def test_request_flags_are_kept(ctx):
+    # requests with different resolution modes in one mix: each is decoded with
+    # its own flags (MRR over a DE stream, Sequential Copying, auto)
+    import torch
+
+    import paper_1606_00519_amd as gmp
+    reqs = [Resident(raw, s) for raw, s in make_requests(n=9, hi=3 << 20, seed=25)]
+    torch.cuda.synchronize()
+    modes = [gmp.MODE_AUTO, gmp.MODE_MRR, gmp.MODE_SC] * 3
+    srv = gmp.Server(ctx, budget_bytes=1 << 31, slots=2)
+    for k, (r, m) in enumerate(zip(reqs, modes)):
+        srv.submit(r.d_in, r.stream, r.out, r.status, m, tag=k)
+    srv.drain(60000)
+    done = srv.poll(64)
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(c["tag"] for c in done) == list(range(len(reqs)))
+    assert all(c["status"] == 0 for c in done)
+    for r in reqs:
+        st, got = r.result()
+        assert np.all(st == 0) and got == r.raw
+
+
+def test_completions_are_per_request(ctx):
+    # a small request submitted together with large ones completes on its own,
+    # before the launch that carries it has finished the large ones
+    import torch
+
+    import paper_1606_00519_amd as gmp
+    text = synth.zipf_text(24 << 20).tobytes()
+    big = [text[i:i + (8 << 20)] for i in (0, 8 << 20)]
+    small = text[16 << 20:(16 << 20) + (64 << 10)]
+    items = []
+    for raw in big + [small]:
+        s = oracle.compress(raw, oracle.CompressParams(block_size=1 << 20, sub_target_raw=16384), threads=8)
+        items.append(Resident(raw, s))
+    torch.cuda.synchronize()
+    srv = gmp.Server(ctx, budget_bytes=1 << 31, slots=1)
+    for k, r in enumerate(items):
+        srv.submit(r.d_in, r.stream, r.out, r.status, gmp.MODE_SC, tag=k)   # slow mode: long launches
+    srv.drain(60000)
+    done = {c["tag"]: c for c in srv.poll(16)}
+    info = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    assert set(done) == {0, 1, 2} and all(c["status"] == 0 for c in done.values())
+    for r in items:
+        st, got = r.result()
+        assert np.all(st == 0) and got == r.raw
+    if done[2]["t_admit_ns"] == done[0]["t_admit_ns"]:   # they shared a launch
+        assert done[2]["t_done_ns"] < max(done[0]["t_done_ns"], done[1]["t_done_ns"])
+    print(f"[gpu] launches {info['launches']}, small done after "
+          f"{(done[2]['t_done_ns'] - done[2]['t_submit_ns']) / 1e6:.2f} ms, large after "
+          f"{(done[0]['t_done_ns'] - done[0]['t_submit_ns']) / 1e6:.2f} ms", flush=True)
