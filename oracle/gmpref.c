@@ -916,16 +916,10 @@ int gmpref_validate_block(const uint8_t* blk, size_t len) {
       if ((payload[byte_off + b / 8] >> (b % 8)) & 1) rc = GMPREF_ESUB;
     byte_off += padded / 8;
   }
-  /* a sequence without a back-reference carries literals and ends its sub-block */
-  if (rc == 0) {
-    size_t si = 0;
-    for (uint32_t s = 0; s < info.n_sub && rc == 0; s++) {
-      uint32_t ns = rd32(idx + IDX_ENTRY * s + 4);
-      for (uint32_t q = 0; q < ns; q++, si++) {
-        if (sv.v[si].match_len == 0 && (sv.v[si].lit_len == 0 || q + 1 != ns)) rc = GMPREF_ESUB;
-      }
-    }
-  }
+  /* (A sequence without a back-reference carries literals and ends its
+     sub-block: decode_tokens only forms one at a sub-block's end symbol, from
+     a non-empty literal run, and checks the index's sequence counts, so the
+     rule needs no separate check here.) */
   if (rc == 0 && info.mode == 1 && !gmpref_de_holds(sv.v, sv.n, info.group)) rc = GMPREF_EDIST;
   if (rc == 0) {
     uint8_t* out = (uint8_t*)malloc(info.raw_len ? info.raw_len : 1);

@@ -7,6 +7,7 @@ import itertools
 import json
 import os
 import struct
+import zlib
 
 import numpy as np
 import pytest
@@ -457,3 +458,117 @@ def test_batch_mix_shape():
     sizes = np.array([i["size"] for i in items])
     assert sizes.min() >= 4096 and sizes.max() <= 4 << 20
     assert 0.4 < np.mean([i["de"] for i in items]) < 0.6
+
+
+def test_generators_match_stored_digests():
+    # tests/golden/generator_digests.json is written by make_generator_digests.py
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mkdig", os.path.join(GOLDEN, "make_generator_digests.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    assert m.digests() == golden("generator_digests.json")
+
+
+# ----------------------------------------------------------------------------- validator rules
+
+def test_validator_rejects_nonzero_padding_bits():
+    # the bits between a sub-block's end and its 128-bit boundary must be zero;
+    # the decoder ignores them, the format check does not
+    data = synth.zipf_text(100_000).tobytes()
+    blk = bytearray(oracle.compress_block(data, P(sub_target_raw=8192)))
+    info = oracle.block_info(bytes(blk))
+    assert oracle.validate_block(bytes(blk)) == 0
+    pay0 = 192 + 16 * info["n_sub"] + 16
+    byte_off, hit = 0, 0
+    for s in range(info["n_sub"]):
+        bit_len = struct.unpack_from("<I", blk, 192 + 16 * s)[0]
+        padded = 128 * ((bit_len + 127) // 128)
+        if padded > bit_len:
+            b = bytearray(blk)
+            pos = bit_len + (padded - bit_len) // 2
+            b[pay0 + byte_off + pos // 8] |= 1 << (pos % 8)
+            assert oracle.validate_block(bytes(b)) == oracle.ESUB
+            assert oracle.decompress_block(bytes(b)) == (0, data)
+            hit += 1
+        byte_off += padded // 8
+    assert hit > 0
+
+
+def test_literal_only_sequence_must_end_its_sub_block():
+    # a literal-only sequence in the middle of a sub-block cannot be told apart
+    # from the next sequence's literals: the decoder sees one sequence fewer
+    # than the index says and rejects the block
+    lits = b"abcdefgh"
+    bad = oracle.encode_block([[3, 0, 0], [2, 4, 3], [3, 0, 0]], lits, [3], P())
+    assert oracle.decompress_block(bad)[0] == oracle.ESUB
+    good = oracle.encode_block([[3, 0, 0], [2, 4, 3], [3, 0, 0]], lits, [1, 2], P())
+    assert oracle.decompress_block(good) == (0, b"abc" + b"de" + b"cdec" + b"fgh")
+
+
+@pytest.mark.parametrize("kind", ["text", "csv"])
+def test_decoded_literal_only_sequences_end_their_sub_blocks(kind):
+    data = synth.slice_of(kind, 0, 600_000).tobytes()
+    blk = oracle.compress_block(data, P(sub_target_raw=4096))
+    rc, seqs, _ = oracle.block_tokens(blk)
+    assert rc == 0
+    info = oracle.block_info(blk)
+    ends = np.cumsum([struct.unpack_from("<I", blk, 192 + 16 * s + 4)[0] for s in range(info["n_sub"])]) - 1
+    zero = np.nonzero(seqs[:, 1] == 0)[0]
+    assert set(zero.tolist()) <= set(ends.tolist())
+    assert np.all(seqs[zero, 0] > 0)
+
+
+# ----------------------------------------------------------------------------- RFC 1951 packing, by zlib
+
+def _deflate_dynamic_header(lens, final: bool) -> tuple[int, int]:
+    """(bits, count) of a DEFLATE dynamic-block header (RFC 1951 section 3.2.7)
+    that declares the given 286 + 30 code lengths.  The code-length alphabet
+    uses a 4-bit code for the lengths 0-15 (symbol v has code v) and none for
+    the repeat codes 16-18."""
+    bits, n = 0, 0
+
+    def put(v, k):  # k bits of v, least significant first
+        nonlocal bits, n
+        bits |= (v & ((1 << k) - 1)) << n
+        n += k
+
+    put(1 if final else 0, 1)
+    put(2, 2)                      # BTYPE 10: dynamic Huffman codes
+    put(286 - 257, 5)
+    put(30 - 1, 5)
+    put(19 - 4, 4)
+    for _ in (16, 17, 18):
+        put(0, 3)
+    for _ in range(16):            # code-length code lengths of 0, 8, 7, 9, ... 15: all 4
+        put(4, 3)
+    for ln in lens:                # each length as its 4-bit code, most significant bit first
+        put(int("{:04b}".format(int(ln))[::-1], 2), 4)
+    return bits, n
+
+
+@pytest.mark.parametrize("kind,de", [("text", 0), ("csv", 1)])
+def test_sub_block_bitstreams_inflate_with_zlib(kind, de):
+    # Every sub-block of a block, given a DEFLATE dynamic header carrying the
+    # block's code lengths, is a DEFLATE block; their concatenation inflates
+    # with the standard library's zlib to the block's original bytes.  This
+    # pins the bit packing, the canonical code assignment, the alphabets and
+    # their extra bits against an implementation that shares nothing with the
+    # oracle.
+    data = synth.slice_of(kind, 0, 200_000).tobytes()
+    blk = oracle.compress_block(data, P(block_size=len(data), sub_target_raw=16384, de=de))
+    info = oracle.block_info(blk)
+    lens = [(blk[32 + i // 2] >> ((i & 1) * 4)) & 15 for i in range(316)]
+    pay0 = 192 + 16 * info["n_sub"] + 16
+    acc, n, off = 0, 0, 0
+    for s in range(info["n_sub"]):
+        bit_len = struct.unpack_from("<I", blk, 192 + 16 * s)[0]
+        hb, hn = _deflate_dynamic_header(lens, s + 1 == info["n_sub"])
+        acc |= hb << n
+        n += hn
+        nbytes = (bit_len + 7) // 8
+        body = int.from_bytes(blk[pay0 + off:pay0 + off + nbytes], "little") & ((1 << bit_len) - 1)
+        acc |= body << n
+        n += bit_len
+        off += 16 * ((bit_len + 127) // 128)
+    raw = acc.to_bytes((n + 7) // 8, "little")
+    assert zlib.decompress(raw, -15) == data
