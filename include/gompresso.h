@@ -185,6 +185,29 @@ gmp_status gmp_decompress_block(gmp_ctx* ctx, const uint8_t* d_block, size_t blo
                                 size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status, uint32_t flags,
                                 void* stream);
 
+/* ---- single block without allocation ----------------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * results as gmp_decompress_block, without a context, on the current device: the
+ * block's token workspace is a fixed device array of GMP_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends, and
+ * the job descriptor travels in the kernel arguments.  The call makes no
+ * hipMalloc, hipFree or other allocating call.  GMP_ERANGE if the block's
+ * workspace (gmp_workspace_bytes) exceeds the array: 32 MiB holds every block
+ * of up to 4 MiB of Zipf text or CSV rows.  Calls on one device share the
+ * array, so calls that overlap on one device (other streams, other threads)
+ * race and must not be made; the array keeps the last call's contents, and the
+ * kernel writes every byte of it that it reads.  gmp_noalloc_init resolves the
+ * array's device address on the current device; the first call does it by
+ * itself, so call gmp_noalloc_init (or the entry point once) before capturing.
+ * Device-side errors go to *d_status only (no context, so no gmp_poll word). */
+#define GMP_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define GMP_ERANGE -13 /* the block is larger than gmp_decompress_block_noalloc's fixed workspace */
+gmp_status gmp_noalloc_init(void);
+gmp_status gmp_decompress_block_noalloc(const uint8_t* d_block, size_t block_len, const void* h_block,
+                                        size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status,
+                                        uint32_t flags, void* stream);
+
 /* ---- whole stream (blocks in parallel, section "Parallel Decompression") ----------- */
 /* Decode a stream.  h_stream: host copy of the whole stream (for the block table and
  * block headers); d_stream: the same bytes on the device, 16-byte aligned, with

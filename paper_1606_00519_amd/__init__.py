@@ -22,8 +22,9 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgompresso_hip.so")
 
-OK, EINVAL, EFORMAT, ECODE, EDIST, ELEN, ESIZE, ESUB, EDEVICE, ENOMEM, EBUSY, ENOSYS, ESTALL = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12)
+OK, EINVAL, EFORMAT, ECODE, EDIST, ELEN, ESIZE, ESUB, EDEVICE, ENOMEM, EBUSY, ENOSYS, ESTALL, ERANGE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12, -13)
+NOALLOC_SCRATCH_BYTES = 32 << 20
 MODE_AUTO, MODE_MRR, MODE_DE, MODE_SC = 0, 1, 2, 3
 FLAG_STATS = 0x100
 FLAG_VERIFY_DE = 0x200
@@ -35,7 +36,7 @@ EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_poll", "gmp
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",
            "gmp_batch_destroy", "gmp_batch_graph_create", "gmp_batch_graph_launch", "gmp_autotune",
            "gmp_server_create", "gmp_server_submit", "gmp_server_poll", "gmp_server_drain", "gmp_server_stats",
-           "gmp_server_destroy", "gmp_workspace_bytes")
+           "gmp_server_destroy", "gmp_workspace_bytes", "gmp_noalloc_init", "gmp_decompress_block_noalloc")
 
 
 class GmpError(RuntimeError):
@@ -109,10 +110,12 @@ def _load():
     L.gmp_workspace_bytes.restype = C.c_uint64
     L.gmp_server_destroy.argtypes = [vp]
     L.gmp_server_destroy.restype = None
+    L.gmp_noalloc_init.argtypes = []
+    L.gmp_decompress_block_noalloc.argtypes = [vp, sz, vp, sz, vp, sz, vp, u32, vp]
     for fn in ("gmp_ctx_create", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
                "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run", "gmp_batch_graph_create",
                "gmp_batch_graph_launch", "gmp_autotune", "gmp_server_create", "gmp_server_submit",
-               "gmp_server_drain", "gmp_server_stats"):
+               "gmp_server_drain", "gmp_server_stats", "gmp_noalloc_init", "gmp_decompress_block_noalloc"):
         getattr(L, fn).restype = i32
     return L
 

@@ -87,6 +87,7 @@ extern "C" const char* gmp_strerror(gmp_status s) {
     case GMP_EBUSY: return "no capacity";
     case GMP_ENOSYS: return "format feature not supported by this decoder";
     case GMP_ESTALL: return "device-side wait exceeded its bound (internal error)";
+    case GMP_ERANGE: return "block too large for the fixed workspace of the allocation-free call";
     default: return "unknown status";
   }
 }
@@ -154,6 +155,12 @@ extern "C" gmp_status gmp_ctx_create(int device, gmp_ctx** out) {
     return GMP_EDEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
+  // the allocation-free call's workspace address on this device, resolved now
+  // (outside any graph capture the caller may start later)
+  if (gmp_noalloc_init() != GMP_OK) {
+    gmp_ctx_destroy(c);
+    return GMP_EDEVICE;
+  }
   *out = c;
   return GMP_OK;
 }

@@ -79,3 +79,7 @@ extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t
 // *word = 0; and *out = *word, *word = 0 in one atomic exchange.
 extern "C" int gmpk_clear_word(int32_t* word, hipStream_t stream);
 extern "C" int gmpk_take_word(int32_t* word, int32_t* out, hipStream_t stream);
+// One block, seven decoder wavefronts, the job descriptor passed by value in
+// the kernel arguments (no device job table).
+extern "C" int gmpk_launch_single(const gmpk::DevJob* h_job, uint32_t flags, int32_t* d_first_err,
+                                  hipStream_t stream);

@@ -2146,6 +2146,15 @@ __global__ __launch_bounds__(block_threads<kDec>()) void inflate_kernel(const De
   run_block<kDec, kMode>(job, flags, first_err);
 }
 
+// One block whose job descriptor travels in the kernel arguments (the launch
+// needs no device job table).
+template <int kDec, int kMode>
+__global__ __launch_bounds__(block_threads<kDec>()) void inflate_single_kernel(DevJob job, uint32_t flags,
+                                                                         int32_t* first_err) {
+  if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
+  run_block<kDec, kMode>(job, flags, first_err);
+}
+
 // Persistent form: workgroups take block indices from a device counter until
 // the job table is exhausted; every workgroup exits once it draws an index
 // past the end.
@@ -2219,6 +2228,28 @@ extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t
     default: return -1;
   }
   if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? 0 : -8;
+}
+
+extern "C" int gmpk_launch_single(const gmpk::DevJob* h_job, uint32_t flags, int32_t* d_first_err,
+                                  hipStream_t stream) {
+  using namespace gmpk;
+  const DevJob job = *h_job;
+  const dim3 grid(1), block(block_threads<7>());
+  switch (flags & GMPK_MODE_MASK) {
+    case GMPK_MODE_AUTO:
+      hipLaunchKernelGGL((inflate_single_kernel<7, GMPK_MODE_AUTO>), grid, block, 0, stream, job, flags, d_first_err);
+      break;
+    case GMPK_MODE_MRR:
+      hipLaunchKernelGGL((inflate_single_kernel<7, GMPK_MODE_MRR>), grid, block, 0, stream, job, flags, d_first_err);
+      break;
+    case GMPK_MODE_DE:
+      hipLaunchKernelGGL((inflate_single_kernel<7, GMPK_MODE_DE>), grid, block, 0, stream, job, flags, d_first_err);
+      break;
+    default:
+      hipLaunchKernelGGL((inflate_single_kernel<7, GMPK_MODE_SC>), grid, block, 0, stream, job, flags, d_first_err);
+      break;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -8;
 }
 
