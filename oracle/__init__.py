@@ -46,13 +46,14 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in (
         "block_size", "window", "max_match", "lmax", "sub_target_raw", "sub_target_seq",
-        "de", "group", "chain", "hash_mode", "staleness")]
+        "de", "group", "chain", "hash_mode", "staleness", "format")]
 
 
 class BlockInfo(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in (
         "version", "mode", "group", "lmax", "raw_len", "window", "max_match",
-        "n_sub", "n_seq", "n_lit", "payload_bytes")] + [("block_bytes", C.c_uint64)]
+        "n_sub", "n_seq", "n_lit", "payload_bytes")] + [("block_bytes", C.c_uint64), ("format", C.c_uint32),
+                                                        ("reserved", C.c_uint32)]
 
 
 @dataclass
@@ -69,6 +70,7 @@ class CompressParams:
     chain: int = 64
     hash_mode: int = 0
     staleness: int = 1024
+    format: int = 0          # 0 Gompresso/Bit, 1 Gompresso/Byte
 
     def to_c(self) -> Params:
         return Params(*[getattr(self, f.name) for f in fields(self)])
@@ -90,6 +92,8 @@ def lib():
                                          C.POINTER(u8p), szp, C.POINTER(C.c_void_p), szp]
         L.gmpref_encode_block.argtypes = [C.c_void_p, C.c_size_t, u8p, C.c_size_t, C.c_void_p, C.c_size_t,
                                           C.POINTER(Params), C.POINTER(u8p), szp]
+        L.gmpref_encode_byte_block.argtypes = [C.c_void_p, C.c_size_t, u8p, C.c_size_t, C.POINTER(Params),
+                                               C.POINTER(u8p), szp]
         L.gmpref_block_info_parse.argtypes = [u8p, C.c_size_t, C.POINTER(BlockInfo)]
         L.gmpref_decompress_block.argtypes = [u8p, C.c_size_t, u8p, C.c_size_t, szp]
         L.gmpref_decompress.argtypes = [u8p, C.c_size_t, u8p, C.c_size_t, szp]
@@ -226,6 +230,19 @@ def encode_block(seqs, lits, sub_seqs, params: CompressParams) -> bytes:
 
 
 # --------------------------------------------------------------------------- decoder
+
+def encode_byte_block(seqs, lits, params: CompressParams) -> bytes:
+    """Gompresso/Byte block of a given token stream (literal runs <= 255 bytes)."""
+    s = _seq_array(seqs)
+    l = _u8(lits) if len(lits) else np.zeros(1, np.uint8)
+    out, n = C.POINTER(C.c_uint8)(), C.c_size_t()
+    pc = params.to_c()
+    rc = lib().gmpref_encode_byte_block(s.ctypes.data, s.shape[0], _ptr(l), len(lits), C.byref(pc), C.byref(out),
+                                        C.byref(n))
+    if rc:
+        raise OracleError(rc, "encode_byte_block")
+    return _take(out, n.value)
+
 def block_info(blk) -> dict:
     a = _u8(blk)
     info = BlockInfo()
@@ -239,7 +256,10 @@ def decompress_block(blk, cap: int | None = None):
     """Returns (status, bytes).  cap defaults to the header's raw_len."""
     a = _u8(blk)
     if cap is None:
-        cap = block_info(a)["raw_len"] if a.size >= BLOCK_HEADER_BYTES else 0
+        try:
+            cap = block_info(a)["raw_len"]
+        except OracleError:
+            cap = 0
     out = np.zeros(max(cap, 1), np.uint8)
     n = C.c_size_t()
     rc = lib().gmpref_decompress_block(_ptr(a), a.size, _ptr(out), cap, C.byref(n))

@@ -70,6 +70,7 @@ void gmpref_default_params(gmpref_params* p) {
   p->chain = 64;
   p->hash_mode = 0;
   p->staleness = 1024;
+  p->format = 0;
 }
 
 /* ======================================================================== */
@@ -437,8 +438,12 @@ int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
                        gmpref_seq** seqs_out, size_t* n_seq_out, uint8_t** lits_out, size_t* n_lits_out,
                        uint32_t** sub_out, size_t* n_sub_out) {
   if (!p || p->window < 1 || p->window > 32768 || p->max_match < 3 || p->max_match > 258 || p->group < 1 ||
-      p->group > 255 || (p->sub_target_raw == 0 && p->sub_target_seq == 0) || n > 0xFFFFFFF0u)
+      p->group > 255 || p->format > 1 || (p->format == 0 && p->sub_target_raw == 0 && p->sub_target_seq == 0) ||
+      n > 0xFFFFFFF0u)
     return GMPREF_EINVAL;
+  /* Byte-level blocks have no sub-blocks (the decoder reads the fixed-size
+     records directly) and keep literal runs within one byte's count */
+  const int byte_fmt = p->format == 1;
   int32_t* head = (int32_t*)malloc(sizeof(int32_t) << HASH_BITS);
   int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (n ? n : 1));
   uint8_t* lits = (uint8_t*)malloc(n ? n : 1);
@@ -512,7 +517,7 @@ int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
       pos += best;
       lit_start = pos;
       int cut = p->sub_target_raw ? (pos - sub_start >= p->sub_target_raw) : (sub_nseq >= p->sub_target_seq);
-      if (cut) {
+      if (cut && !byte_fmt) {
         if (u32_push(&subs, sub_nseq)) err = 1;
         sub_nseq = 0;
         sub_start = pos;
@@ -521,7 +526,11 @@ int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
       lits[nl++] = in[pos];
       INSERT(pos);
       pos++;
-      if (p->sub_target_raw && pos - sub_start >= p->sub_target_raw) {
+      if (byte_fmt && pos - lit_start == 255) {
+        /* a literal run as long as a record can hold becomes a sequence of its own */
+        CLOSE_SEQ(255, 0, 0);
+        lit_start = pos;
+      } else if (!byte_fmt && p->sub_target_raw && pos - sub_start >= p->sub_target_raw) {
         /* the sub-block ends inside a literal run: the run becomes a
            sequence without a back-reference */
         CLOSE_SEQ(pos - lit_start, 0, 0);
@@ -533,7 +542,7 @@ int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
     }
   }
   if (!err && pos > lit_start) CLOSE_SEQ(pos - lit_start, 0, 0);
-  if (!err && sub_nseq > 0)
+  if (!err && sub_nseq > 0 && !byte_fmt)
     if (u32_push(&subs, sub_nseq)) err = 1;
 #undef INSERT
 #undef CLOSE_SEQ
@@ -549,6 +558,115 @@ int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
   return GMPREF_OK;
 }
 
+
+/* ======================================================================== */
+/* Gompresso/Byte: the token stream written with a direct byte-level        */
+/* encoding (section "Gompresso Overview"), one fixed-size record per       */
+/* sequence and the literal bytes after the records.                        */
+/* ======================================================================== */
+#define BYTE_MAGIC 0x59504D47u
+#define BYTE_HDR 32
+
+static size_t pad16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+int gmpref_encode_byte_block(const gmpref_seq* seqs, size_t n_seq, const uint8_t* lits, size_t n_lits,
+                             const gmpref_params* p, uint8_t** out, size_t* out_len) {
+  if (!p || n_seq > 0x3FFFFFFFu || n_lits > 0xFFFFFFFFu) return GMPREF_EINVAL;
+  uint64_t raw = 0, lit_sum = 0;
+  for (size_t i = 0; i < n_seq; i++) {
+    const gmpref_seq* q = &seqs[i];
+    if (q->lit_len > 255 || q->dist > 65535) return GMPREF_EINVAL;
+    if (q->match_len == 0 ? q->dist != 0 : (q->match_len < 3 || q->match_len > 258 || q->dist == 0))
+      return GMPREF_EINVAL;
+    raw += q->lit_len + q->match_len;
+    lit_sum += q->lit_len;
+  }
+  if (lit_sum != n_lits || raw > 0xFFFFFFFFu) return GMPREF_EINVAL;
+  const size_t rec_bytes = pad16(4 * n_seq), total = BYTE_HDR + rec_bytes + pad16(n_lits) + 16;
+  uint8_t* b = (uint8_t*)calloc(total, 1);
+  if (!b) return GMPREF_ENOMEM;
+  wr32(b, BYTE_MAGIC);
+  b[4] = 1;
+  b[5] = (uint8_t)(p->de ? 1 : 0);
+  b[6] = (uint8_t)p->group;
+  wr32(b + 8, (uint32_t)raw);
+  wr32(b + 12, p->window);
+  wr16(b + 16, (uint16_t)p->max_match);
+  wr32(b + 20, (uint32_t)n_seq);
+  wr32(b + 24, (uint32_t)n_lits);
+  for (size_t i = 0; i < n_seq; i++) {
+    const gmpref_seq* q = &seqs[i];
+    const uint32_t m = q->match_len ? q->match_len - 3 : 0;
+    wr32(b + BYTE_HDR + 4 * i, q->lit_len | (m << 8) | (q->dist << 16));
+  }
+  if (n_lits) memcpy(b + BYTE_HDR + rec_bytes, lits, n_lits);
+  *out = b;
+  *out_len = total;
+  return GMPREF_OK;
+}
+
+static int byte_info_parse(const uint8_t* blk, size_t len, gmpref_block_info* info) {
+  if (len < BYTE_HDR || rd32(blk) != BYTE_MAGIC || blk[4] != 1) return GMPREF_EFORMAT;
+  memset(info, 0, sizeof(*info));
+  info->format = 1;
+  info->version = 1;
+  info->mode = blk[5];
+  info->group = blk[6];
+  info->raw_len = rd32(blk + 8);
+  info->window = rd32(blk + 12);
+  info->max_match = rd16(blk + 16);
+  info->n_seq = rd32(blk + 20);
+  info->n_lit = rd32(blk + 24);
+  if (info->mode > 1 || info->group < 1 || blk[7] != 0 || info->window < 1 || info->window > 32768 ||
+      info->max_match < 3 || info->max_match > 258 || rd16(blk + 18) != 0 || rd32(blk + 28) != 0 ||
+      info->n_seq > 0x3FFFFFFFu)
+    return GMPREF_EFORMAT;
+  const uint64_t payload = pad16(4 * (size_t)info->n_seq) + pad16(info->n_lit) + 16;
+  if (payload > 0xFFFFFFFFu) return GMPREF_EFORMAT;
+  info->payload_bytes = (uint32_t)payload;
+  info->block_bytes = BYTE_HDR + payload;
+  if (info->block_bytes > len) return GMPREF_EFORMAT;
+  return GMPREF_OK;
+}
+
+/* The records of a byte-level block, checked: first the totals against the
+   header (ESUB), then each record in order, with the first failing check of
+   the first failing record deciding the class: a distance field of 0 with a
+   nonzero match field (EFORMAT), a match longer than max_match (ELEN), a
+   distance beyond the window or before the block's start (EDIST). */
+static int byte_tokens(const uint8_t* blk, size_t len, gmpref_block_info* info, seqvec* sv, uint8_t** lits_out,
+                       size_t* nl_out) {
+  int rc = byte_info_parse(blk, len, info);
+  if (rc) return rc;
+  const uint8_t* rec = blk + BYTE_HDR;
+  uint64_t lit_sum = 0, out_sum = 0;
+  for (uint32_t i = 0; i < info->n_seq; i++) {
+    const uint32_t r = rd32(rec + 4 * (size_t)i);
+    const uint32_t d = r >> 16;
+    lit_sum += r & 0xFF;
+    out_sum += (r & 0xFF) + (d ? ((r >> 8) & 0xFF) + 3 : 0);
+  }
+  if (lit_sum != info->n_lit || out_sum != info->raw_len) return GMPREF_ESUB;
+  uint64_t produced = 0;
+  for (uint32_t i = 0; i < info->n_seq; i++) {
+    const uint32_t r = rd32(rec + 4 * (size_t)i);
+    const uint32_t lit = r & 0xFF, mf = (r >> 8) & 0xFF, d = r >> 16;
+    const uint32_t m = d ? mf + 3 : 0;
+    produced += lit;
+    if (d == 0 && mf != 0) return GMPREF_EFORMAT;
+    if (m > info->max_match) return GMPREF_ELEN;
+    if (d && (d > info->window || d > produced)) return GMPREF_EDIST;
+    if (seq_push(sv, lit, m, d)) return GMPREF_ENOMEM;
+    produced += m;
+  }
+  uint8_t* lits = (uint8_t*)malloc(info->n_lit ? info->n_lit : 1);
+  if (!lits) return GMPREF_ENOMEM;
+  if (info->n_lit) memcpy(lits, rec + pad16(4 * (size_t)info->n_seq), info->n_lit);
+  *lits_out = lits;
+  *nl_out = info->n_lit;
+  return GMPREF_OK;
+}
+
 int gmpref_compress_block(const uint8_t* in, size_t n, const gmpref_params* p, uint8_t** out, size_t* out_len) {
   gmpref_seq* seqs = NULL;
   uint8_t* lits = NULL;
@@ -556,7 +674,10 @@ int gmpref_compress_block(const uint8_t* in, size_t n, const gmpref_params* p, u
   size_t ns = 0, nl = 0, nsub = 0;
   int rc = gmpref_parse_block(in, n, p, &seqs, &ns, &lits, &nl, &subs, &nsub);
   if (rc) return rc;
-  rc = gmpref_encode_block(seqs, ns, lits, nl, subs, nsub, p, out, out_len);
+  if (p->format == 1)
+    rc = gmpref_encode_byte_block(seqs, ns, lits, nl, p, out, out_len);
+  else
+    rc = gmpref_encode_block(seqs, ns, lits, nl, subs, nsub, p, out, out_len);
   free(seqs);
   free(lits);
   free(subs);
@@ -607,8 +728,11 @@ int gmpref_compress(const uint8_t* in, size_t n, const gmpref_params* p, uint8_t
 /* ======================================================================== */
 int gmpref_block_info_parse(const uint8_t* blk, size_t len, gmpref_block_info* info) {
   if (!blk || !info) return GMPREF_EINVAL;
+  if (len >= 4 && rd32(blk) == BYTE_MAGIC) return byte_info_parse(blk, len, info);
   if (len < HDR_BYTES) return GMPREF_EFORMAT;
   if (rd32(blk) != 0x42504D47u || blk[4] != 1) return GMPREF_EFORMAT;
+  info->format = 0;
+  info->reserved = 0;
   info->version = blk[4];
   info->mode = blk[5];
   info->group = blk[6];
@@ -707,6 +831,7 @@ static int canon_decode(const canon_t* h, bitr* r) {
    the sizes in the header and decoded with the block's two codes). */
 static int decode_tokens(const uint8_t* blk, size_t len, gmpref_block_info* info, seqvec* sv, uint8_t** lits_out,
                          size_t* nl_out) {
+  if (len >= 4 && rd32(blk) == BYTE_MAGIC) return byte_tokens(blk, len, info, sv, lits_out, nl_out);
   int rc = gmpref_block_info_parse(blk, len, info);
   if (rc) return rc;
   uint8_t lens[N_LL + N_D];
@@ -905,6 +1030,15 @@ int gmpref_validate_block(const uint8_t* blk, size_t len) {
   size_t nl = 0;
   int rc = decode_tokens(blk, len, &info, &sv, &lits, &nl);
   if (rc) { free(sv.v); return rc; }
+  if (info.format == 1) {
+    /* byte-level block: every padding byte is zero */
+    const size_t r_end = BYTE_HDR + 4 * (size_t)info.n_seq, l0 = BYTE_HDR + pad16(4 * (size_t)info.n_seq);
+    for (size_t k = r_end; k < l0 && rc == 0; k++)
+      if (blk[k]) rc = GMPREF_ESUB;
+    for (size_t k = l0 + info.n_lit; k < info.block_bytes && rc == 0; k++)
+      if (blk[k]) rc = GMPREF_ESUB;
+    info.n_sub = 0;
+  }
   /* padding bits after each sub-block are zero */
   const uint8_t* idx = blk + HDR_BYTES;
   const uint8_t* payload = blk + HDR_BYTES + (size_t)IDX_ENTRY * info.n_sub + 16;

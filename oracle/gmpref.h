@@ -65,6 +65,30 @@
  * back-reference (section "LZ77 Decompression").  A literal run that is
  * closed by the end of a sub-block forms a sequence with match length 0.
  *
+ * Byte-level block (Gompresso/Byte, section "Gompresso Overview": the token
+ * streams are written with a direct byte-level encoding and no Huffman stage,
+ * so the decoder reads them straight from the compressed block):
+ *   off   0  u32 magic 'GMPY' (0x59504D47)
+ *   off   4  u8  version (1)
+ *   off   5  u8  mode     0 = ordinary LZ77 stream, 1 = DE stream
+ *   off   6  u8  group    G
+ *   off   7  u8  reserved (0)
+ *   off   8  u32 raw_len
+ *   off  12  u32 window   1..32768
+ *   off  16  u16 max_match 3..258
+ *   off  18  u16 reserved (0)
+ *   off  20  u32 n_seq    sequences (4-byte records)
+ *   off  24  u32 n_lit    literal bytes
+ *   off  28  u32 reserved (0)
+ *   off  32  n_seq records, one u32 each, little-endian:
+ *              bits 0-7   literal length 0..255
+ *              bits 8-15  match length - 3 (0 when the sequence has no match)
+ *              bits 16-31 distance 1..32768, 0 = no back-reference
+ *            then zero bytes up to a multiple of 16
+ *   then the n_lit literal bytes, zero bytes up to a multiple of 16, and 16
+ *   more zero bytes.  Literal runs longer than 255 bytes are split into
+ *   literal-only sequences, which may appear anywhere.
+ *
  * Stream (a whole input):
  *   off 0  u32 magic 'GMPF' (0x46504D47), u16 version (1), u16 flags (0),
  *          u32 block_size, u32 n_blocks, u64 raw_total, u64 reserved
@@ -112,12 +136,16 @@ typedef struct {
   uint32_t chain;          /* maximum match candidates examined per position */
   uint32_t hash_mode;      /* 0 = hash chains, 1 = single-entry table with minimal staleness */
   uint32_t staleness;      /* hash_mode 1: replace an entry only if it is more than this many bytes old */
+  uint32_t format;         /* 0 = Gompresso/Bit (Huffman-coded sub-blocks), 1 = Gompresso/Byte (byte-level
+                              records; literal runs of at most 255 bytes; no sub-blocks) */
 } gmpref_params;
 
 typedef struct {
   uint32_t version, mode, group, lmax, raw_len, window, max_match;
   uint32_t n_sub, n_seq, n_lit, payload_bytes;
   uint64_t block_bytes;    /* total bytes of the block including header, index and payload */
+  uint32_t format;         /* 0 = Bit ('GMPB'), 1 = Byte ('GMPY'; lmax and n_sub are 0) */
+  uint32_t reserved;
 } gmpref_block_info;
 
 void gmpref_default_params(gmpref_params* p);
@@ -131,6 +159,10 @@ int gmpref_compress_block(const uint8_t* in, size_t n, const gmpref_params* p,
 int gmpref_parse_block(const uint8_t* in, size_t n, const gmpref_params* p,
                        gmpref_seq** seqs, size_t* n_seq, uint8_t** lits, size_t* n_lits,
                        uint32_t** sub_seqs, size_t* n_sub);
+/* Byte-level block of a given token stream (every lit_len <= 255; sequences
+ * without a match have dist 0).  mode/group/window/max_match come from p. */
+int gmpref_encode_byte_block(const gmpref_seq* seqs, size_t n_seq, const uint8_t* lits, size_t n_lits,
+                             const gmpref_params* p, uint8_t** out, size_t* out_len);
 /* Encode a given token stream (tests build adversarial streams with it).
  * sub_seqs[i] = sequences in sub-block i; mode/group/window/max_match/lmax
  * come from p and are written to the header unchecked. */

@@ -572,3 +572,96 @@ def test_sub_block_bitstreams_inflate_with_zlib(kind, de):
         off += 16 * ((bit_len + 127) // 128)
     raw = acc.to_bytes((n + 7) // 8, "little")
     assert zlib.decompress(raw, -15) == data
+
+
+# ----------------------------------------------------------------------------- Gompresso/Byte
+
+def test_byte_worked_example():
+    g = golden("byte_worked_example.json")
+    blk = oracle.encode_byte_block(g["sequences"], g["literals"].encode(), P())
+    # header: 'GMPY', version 1, mode 0, G 64, raw 7, window 32768, max 258, 2 sequences, 4 literal bytes
+    want = (b"GMPY" + bytes([1, 0, 64, 0]) + struct.pack("<IIHHIII", 7, 32768, 258, 0, 2, 4, 0) +
+            struct.pack("<II", 3 | (0 << 8) | (3 << 16), 1) + bytes(8) + b"aacb" + bytes(12) + bytes(16))
+    assert blk == want == bytes.fromhex(g["block_hex"])
+    assert oracle.decompress_block(blk) == (0, g["decoded"].encode())
+    info = oracle.block_info(blk)
+    assert info["format"] == 1 and info["block_bytes"] == len(blk) and info["n_sub"] == 0
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("de", [0, 1])
+def test_byte_round_trip(name, de):
+    data = CASES[name]
+    s = oracle.compress(data, P(block_size=1 << 18, format=1, de=de), threads=4)
+    assert oracle.decompress(s) == (0, data)
+    for blk, _ in oracle.stream_blocks(s)[0]:
+        assert oracle.validate_block(blk) == 0
+        rc, seqs, lits = oracle.block_tokens(blk)
+        assert rc == 0
+        if len(seqs):
+            assert seqs[:, 0].max() <= 255
+            # literal-only sequences: only where a run reached 255 bytes, or at the block's end
+            lo = np.nonzero(seqs[:, 1] == 0)[0]
+            assert all(seqs[i, 0] == 255 or i == len(seqs) - 1 for i in lo)
+        if de:
+            assert oracle.de_holds(seqs, 64)
+            r, _ = oracle.mrr_rounds(seqs, 64)
+            assert set(r.tolist()) <= {0, 1}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_byte_blocks_decode_like_the_textbook_expander(seed):
+    seqs, lits = synth.random_tokens(3000, seed, overlap_frac=0.3)
+    seqs = np.asarray(seqs)
+    # split literal runs longer than a record holds into literal-only sequences
+    out_seqs, li = [], 0
+    for lit, m, d in seqs.tolist():
+        while lit > 255:
+            out_seqs.append([255, 0, 0])
+            lit -= 255
+        out_seqs.append([lit, m, d])
+    blk = oracle.encode_byte_block(out_seqs, lits, P())
+    want = expand(out_seqs, lits)
+    assert oracle.decompress_block(blk) == (0, want)
+
+
+def test_byte_error_classes_follow_record_order():
+    lits = bytes(range(40))
+    enc = lambda seqs, **kw: oracle.encode_byte_block(seqs, lits, P(**kw))
+    good = [[10, 4, 5], [10, 0, 0], [10, 5, 20], [10, 3, 1]]
+    assert oracle.decompress_block(enc(good))[0] == 0
+
+    def with_record(blk, i, lit, mfield, dist):
+        b = bytearray(blk)
+        struct.pack_into("<I", b, 32 + 4 * i, lit | (mfield << 8) | (dist << 16))
+        return bytes(b)
+
+    blk = enc(good)
+    # totals are checked first: a literal count that disagrees with the header
+    assert oracle.decompress_block(with_record(blk, 1, 11, 0, 0), 52)[0] == oracle.ESUB
+    # a distance of 0 with a match field (the totals ignore the field of a record without a match)
+    b = with_record(blk, 1, 10, 2, 0)
+    assert oracle.decompress_block(b)[0] == oracle.EFORMAT
+    # a match longer than the header's max_match: ELEN
+    assert oracle.decompress_block(enc([[10, 4, 5], [10, 0, 0], [10, 73, 20], [10, 3, 1]], max_match=64))[0] \
+        == oracle.ELEN
+    # ... unless an earlier record fails first: record 0 reaches before the block's start
+    assert oracle.decompress_block(enc([[10, 4, 15], [10, 0, 0], [10, 73, 20], [10, 3, 1]], max_match=64))[0] \
+        == oracle.EDIST
+    # a distance beyond the window
+    blk4 = enc([[10, 4, 5], [10, 0, 0], [10, 5, 20], [10, 3, 1]], window=8)
+    assert oracle.decompress_block(blk4)[0] == oracle.EDIST
+    assert oracle.validate_block(blk4) == oracle.EDIST
+    # nonzero padding after the literals (40 of them, from offset 48): only the format check rejects it
+    b = bytearray(blk)
+    b[48 + 40] = 1
+    assert oracle.decompress_block(bytes(b))[0] == 0 and oracle.validate_block(bytes(b)) == oracle.ESUB
+
+
+def test_byte_and_bit_streams_decode_alike():
+    data = synth.zipf_text(2 << 20).tobytes()
+    for de in (0, 1):
+        bit = oracle.compress(data, P(de=de), threads=4)
+        byt = oracle.compress(data, P(de=de, format=1), threads=4)
+        assert oracle.decompress(bit)[1] == oracle.decompress(byt)[1] == data
+        assert len(byt) > len(bit)   # no entropy stage: a lower compression ratio
