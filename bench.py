@@ -83,29 +83,72 @@ def oracle_leg(size: int, threads: int, cpu_seconds: float):
             f"in {time.time() - t0:.1f}s")
     baseline = None
     if cpu_seconds > 0:
-        blocks = [(blk, len(blk)) for m in ("mrr", "de") for blk, _ in oracle.stream_blocks(streams[m])[0]]
-        raw_per_pass = 2 * size
-
-        def one(b):
-            rc, out = oracle.decompress_block(b[0])
-            assert rc == 0
-            return len(out)
-
-        passes, t0 = 0, time.time()
-        with ThreadPoolExecutor(threads) as ex:
-            while True:
-                assert sum(ex.map(one, blocks)) == raw_per_pass
-                passes += 1
-                el = time.time() - t0
-                if el * threads >= cpu_seconds or el > 30:
-                    break
-        baseline = {"value": round(raw_per_pass * passes / el / 1e9, 4), "unit": "GB/s", "cores": threads,
-                    "kind": "oracle",
-                    "sample": f"{passes} pass(es) over all {len(blocks)} blocks of both streams "
-                              f"({raw_per_pass >> 20} MiB decompressed per pass), block-parallel over "
-                              f"{threads} threads with a shared block queue; {el:.1f}s wall"}
-        log(f"cpu baseline: {baseline['value']} GB/s on {threads} threads ({passes} passes, {el:.1f}s)")
+        baseline = cpu_baseline(streams, size, threads, cpu_seconds)
     return data, streams, baseline
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(streams: dict, size: int, threads: int, cpu_seconds: float) -> dict:
+    """The oracle decoder (plain C, one block per call) on the host cores, on
+    the headline data: all-core block-parallel (the paper's CPU method: a
+    shared queue of blocks, each thread takes the next block when it
+    finishes) over both streams, and single-threaded over a sample of blocks;
+    median of 5 passes each, the sample sized to about cpu_seconds of CPU work."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    blocks = [blk for m in ("mrr", "de") for blk, _ in oracle.stream_blocks(streams[m])[0]]
+    raw_all = 2 * size
+
+    def one(b):
+        rc, out = oracle.decompress_block(b)
+        assert rc == 0
+        return len(out)
+
+    # a first pass sizes the sample
+    t0 = time.perf_counter()
+    n_probe = min(8, len(blocks))
+    probe_raw = sum(one(b) for b in blocks[:n_probe])
+    per_byte = (time.perf_counter() - t0) / probe_raw          # one core's seconds per byte
+    # all-core: the whole of both streams per pass if that fits the budget, else a prefix
+    share = min(1.0, cpu_seconds / 2 / 5 / (per_byte * raw_all))
+    sample = blocks[:max(threads, int(len(blocks) * share))]
+    times = []
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(5):
+            t0 = time.perf_counter()
+            sample_raw = sum(ex.map(one, sample))
+            times.append(time.perf_counter() - t0)
+    allcore = sample_raw / float(np.median(times)) / 1e9
+    # single thread: blocks of both modes, alternately
+    n1 = max(2, int(cpu_seconds / 2 / 5 / (per_byte * (1 << 20))))
+    half = len(blocks) // 2
+    single = [blocks[i // 2 + (half if i % 2 else 0)] for i in range(min(n1, len(blocks)))]
+    times1 = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        raw1 = sum(one(b) for b in single)
+        times1.append(time.perf_counter() - t0)
+    st = raw1 / float(np.median(times1)) / 1e9
+    res = {"value": round(allcore, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "single_thread_GBps": round(st, 4), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"all-core: {len(sample)} blocks of the headline MRR and DE streams "
+                     f"({sample_raw >> 20} MiB decompressed per pass), block-parallel over {threads} threads "
+                     f"with a shared block queue, median of 5 passes; single thread: {len(single)} blocks "
+                     f"({raw1 >> 20} MiB) of both streams, median of 5 passes"}
+    log(f"cpu baseline: {res['value']} GB/s on {threads} threads, {res['single_thread_GBps']} GB/s on one "
+        f"({res['cpu_model']})")
+    return res
 
 
 def launch_shape(waves: int) -> str:
@@ -116,47 +159,168 @@ def launch_shape(waves: int) -> str:
 
 
 # ----------------------------------------------------------------------------- GPU leg
-def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int, waves: int):
-    import numpy as np
+class StreamRun:
+    """One compressed stream resident on the device, decoded as one batch (one
+    job per block, the output contiguous): the launch bench.py times.  A second
+    job table over the same buffers records per-block phase stamps, per-group
+    rounds and per-block counters (GMP_FLAG_STATS) in an untimed run.  The job
+    table is set up from the block headers by the library's own parser
+    (gmp_block_info_parse)."""
+
+    def __init__(self, ctx, s: bytes, raw: int):
+        import struct
+
+        import torch
+
+        import paper_1606_00519_amd as gmp
+        self.gmp = gmp
+        nb, bs, total = gmp.stream_info(s)
+        assert total == raw
+        offs = struct.unpack_from(f"<{nb + 1}Q", s, 32)
+        self.d_in = torch.frombuffer(bytearray(s), dtype=torch.uint8).cuda()
+        self.out = torch.empty(raw, dtype=torch.uint8, device="cuda")
+        self.status = torch.full((max(nb, 1),), 99, dtype=torch.int32, device="cuda")
+        infos = [gmp.block_info(s[offs[b]:offs[b + 1]]) for b in range(nb)]
+        self.n_groups = [(i["n_seq"] + 63) // 64 for i in infos]
+        goff = np.concatenate([[0], np.cumsum(self.n_groups)]).astype(np.int64)
+        self.goff = goff
+        self.rounds = torch.zeros((max(int(goff[-1]), 1),), dtype=torch.uint8, device="cuda")
+        self.times = torch.zeros((max(nb, 1), 4), dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros((max(nb, 1), gmp.STATS_WORDS), dtype=torch.int32, device="cuda")
+        jobs, sjobs = [], []
+        for b, i in enumerate(infos):
+            args = (self.d_in.data_ptr() + offs[b], offs[b + 1] - offs[b], self.out.data_ptr() + b * bs,
+                    i["raw_len"], i["n_seq"], i["n_lit"])
+            jobs.append(gmp.Job(*args, None, None, None, i["format"]))
+            sjobs.append(gmp.Job(*args, self.rounds.data_ptr() + int(goff[b]), self.times.data_ptr() + 32 * b,
+                                 self.stats.data_ptr() + 4 * gmp.STATS_WORDS * b, i["format"]))
+        self.batch = ctx.batch_create(jobs, self.status)
+        self.sbatch = ctx.batch_create(sjobs, self.status)
+        self.blocks, self.comp, self.raw = nb, len(s), raw
+
+    def run(self, flags: int, waves: int) -> None:
+        self.batch.run(flags, waves=waves, persistent=False)
+
+    def check(self, data: bytes, what: str) -> None:
+        st = self.status.cpu().numpy()
+        if not np.all(st[:self.blocks] == 0):
+            raise RuntimeError(f"{what}: device status {st[st != 0][:8]}")
+        if not np.array_equal(self.out.cpu().numpy(), np.frombuffer(data, np.uint8)):
+            raise RuntimeError(f"{what}: GPU output differs from the original data")
+
+    def stats_run(self, flags: int, waves: int) -> dict:
+        """Untimed run with GMP_FLAG_STATS: mean phase times (device clock),
+        the rounds histogram over groups with back-references, and the
+        paper's bytes per round (bytes copied in round r over all groups,
+        divided by the number of groups)."""
+        import torch
+        self.sbatch.run(flags | self.gmp.FLAG_STATS, waves=waves, persistent=False)
+        torch.cuda.synchronize()
+        t = self.times.cpu().numpy().astype(np.int64)[:self.blocks]
+        d = np.diff(t, axis=1) * 10 / 1e3  # microseconds: tables, sub-block decode, resolution
+        span = (t[:, 3].max() - t[:, 0].min()) * 10 / 1e3
+        r = self.rounds.cpu().numpy()[:int(self.goff[-1])] & 0x7F
+        c = self.stats.cpu().numpy().astype(np.int64)[:self.blocks]
+        groups = int(len(r))
+        hist = np.bincount(r, minlength=65)
+        rb = c[:, self.gmp.STAT_ROUND_BYTES:self.gmp.STAT_ROUND_BYTES + 64].sum(axis=0)
+        last = int(np.max(np.nonzero(rb)[0])) + 1 if rb.any() else 0
+        paths = np.bincount(c[:, self.gmp.STAT_A2_PATH], minlength=4)
+        return {"phases": {"tables_us": round(float(d[:, 0].mean()), 2),
+                           "huffman_us": round(float(d[:, 1].mean()), 2),
+                           "huffman_us_max": round(float(d[:, 1].max()), 2),
+                           "lz_us": round(float(d[:, 2].mean()), 2), "lz_us_max": round(float(d[:, 2].max()), 2),
+                           "launch_span_us": round(float(span), 2)},
+                "groups": groups,
+                "rounds_mean": round(float(r[r > 0].mean()), 3) if (r > 0).any() else 0.0,
+                "rounds_hist": {int(k): int(v) for k, v in enumerate(hist) if v and k > 0},
+                "groups_without_backrefs": int(hist[0]),
+                "round_bytes": [int(x) for x in rb[:last]],
+                "bytes_per_round": [round(float(x) / max(groups, 1), 3) for x in rb[:last]],
+                "a2_paths": {"segmented": int(paths[1]), "per_sub_block": int(paths[2]), "byte_level": int(paths[3])},
+                "repaired_lanes": int(c[:, self.gmp.STAT_REPAIRED].sum()),
+                "split_groups": int(c[:, self.gmp.STAT_SPLIT].sum())}
+
+    def close(self) -> None:
+        self.batch.close()
+        self.sbatch.close()
+
+
+def time_modes(runs: dict, steps: int, warmup: int, waves: int) -> dict:
+    """Each run alone: warm-up launches, then `steps` launches each bracketed
+    by HIP events on the launch stream; mean and median kernel ms."""
+    import torch
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, (r, flags) in runs.items():
+        for _ in range(warmup):
+            r.run(flags, waves)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream)
+            r.run(flags, waves)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in evs]
+        res[name] = {"mean": float(np.mean(ms)), "median": float(np.median(ms)), "min": float(np.min(ms))}
+    return res
+
+
+def mode_entry(raw: int, comp: int, ms: dict, stats: dict | None, copy_gbps: float | None) -> dict:
+    t = ms["mean"] / 1e3
+    alg = (raw + comp) / t / 1e9
+    e = {"GBps": round(raw / t / 1e9, 3), "kernel_ms": round(ms["mean"], 4),
+         "kernel_ms_median": round(ms["median"], 4), "ratio": round(raw / comp, 4), "compressed_bytes": comp,
+         "hbm_GBps": round(alg, 2), "hbm_frac": round(alg / HBM_PEAK_GBPS, 5)}
+    if copy_gbps:
+        e["copy_frac"] = round(alg / copy_gbps, 5)
+    if stats:
+        e.update(stats)
+    return e
+
+
+def copy_reference(size: int, steps: int) -> dict:
+    """A plain device-to-device copy of `size` bytes (torch's copy kernel),
+    timed like the decoder: the practical HBM bound the decoder's traffic is
+    also reported against."""
+    import torch
+    src = torch.empty(size, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        dst.copy_(src)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": size, "ms": round(ms, 4), "GBps": round(2 * size / (ms / 1e3) / 1e9, 2),
+            "what": "torch device-to-device copy of the headline output size; GB/s counts bytes read + written"}
+
+
+def gpu_leg(ctx, data: bytes, streams: dict, steps: int, warmup: int, waves: int):
+    """The headline: one step decodes the MRR stream and then the DE stream of
+    the same data, one launch each."""
     import torch
 
     import paper_1606_00519_amd as gmp
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    ctx = gmp.Context(0)
     size = len(data)
-    runs = {}
-    for mode in ("mrr", "de"):
-        s = streams[mode]
-        d_in = torch.frombuffer(bytearray(s), dtype=torch.uint8).to(dev)
-        out = torch.empty(size, dtype=torch.uint8, device=dev)
-        import oracle
-        blocks, bs, total = oracle.stream_blocks(s)
-        import struct
-        offs = struct.unpack_from(f"<{len(blocks) + 1}Q", s, 32)
-        jobs = []
-        for b, (blk, o) in enumerate(blocks):
-            info = gmp.block_info(blk)
-            jobs.append(gmp.Job(d_in.data_ptr() + offs[b], len(blk), out.data_ptr() + o, info["raw_len"],
-                                info["n_seq"], info["n_lit"], None))
-        status = torch.full((len(jobs),), 99, dtype=torch.int32, device=dev)
-        batch = ctx.batch_create(jobs, status)
-        # a second job table over the same buffers records per-phase device timestamps
-        times = torch.zeros((len(jobs), 4), dtype=torch.int64, device=dev)
-        for b, j in enumerate(jobs):
-            j.d_times = times.data_ptr() + 32 * b
-        tbatch = ctx.batch_create(jobs, status)
-        runs[mode] = {"batch": batch, "tbatch": tbatch, "times": times, "out": out, "d_in": d_in,
-                      "status": status, "comp": len(s), "flags": gmp.MODE_MRR if mode == "mrr" else gmp.MODE_DE,
-                      "blocks": len(jobs)}
+    runs = {m: (StreamRun(ctx, streams[m], size), gmp.MODE_MRR if m == "mrr" else gmp.MODE_DE)
+            for m in ("mrr", "de")}
     stream = torch.cuda.current_stream()
 
     def step(evs=None):
-        for k, mode in enumerate(("mrr", "de")):
-            r = runs[mode]
+        for mode, (r, flags) in runs.items():
             if evs is not None:
                 evs[mode][0].record(stream)
-            r["batch"].run(r["flags"], waves=waves, persistent=False)
+            r.run(flags, waves)
             if evs is not None:
                 evs[mode][1].record(stream)
 
@@ -164,40 +328,83 @@ def gpu_leg(data: bytes, streams: dict, steps: int, warmup: int, waves: int):
         step()
     torch.cuda.synchronize()
     ev_list = [{m: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for m in ("mrr", "de")} for _ in range(steps)]
+                for m in runs} for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         step(ev_list[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = {m: float(np.mean([e[m][0].elapsed_time(e[m][1]) for e in ev_list])) for m in ("mrr", "de")}
-    # correctness of what was timed
-    ref = np.frombuffer(data, np.uint8)
-    phases = {}
-    for mode, r in runs.items():
-        if not np.array_equal(r["out"].cpu().numpy(), ref):
-            raise RuntimeError(f"{mode}: GPU output differs from the original data")
-        # untimed extra run: device wall-clock stamps per block (100 MHz ticks)
-        r["tbatch"].run(r["flags"] | gmp.FLAG_STATS, waves=waves, persistent=False)
-        torch.cuda.synchronize()
-        t = r["times"].cpu().numpy().astype(np.int64)
-        d = np.diff(t, axis=1) * 10 / 1e3  # microseconds: tables, sub-block decode, resolution
-        span = (t[:, 3].max() - t[:, 0].min()) * 10 / 1e3
-        phases[mode] = {"tables_us": round(float(d[:, 0].mean()), 2), "huffman_us": round(float(d[:, 1].mean()), 2),
-                        "huffman_us_max": round(float(d[:, 1].max()), 2), "lz_us": round(float(d[:, 2].mean()), 2),
-                        "lz_us_max": round(float(d[:, 2].max()), 2), "launch_span_us": round(float(span), 2)}
-    for mode, r in runs.items():
-        st = r["status"].cpu().numpy()
-        if not np.all(st == 0):
-            raise RuntimeError(f"{mode}: device status {st[st != 0][:8]}")
-        if not np.array_equal(r["out"].cpu().numpy(), ref):
-            raise RuntimeError(f"{mode}: GPU output differs from the original data")
-    for r in runs.values():
-        r["batch"].close()
-        r["tbatch"].close()
-    ctx.close()
-    return wall, kernel_ms, {m: runs[m]["comp"] for m in runs}, runs["mrr"]["blocks"], phases
+    kernel_ms = {m: {"mean": float(np.mean([e[m][0].elapsed_time(e[m][1]) for e in ev_list])),
+                     "median": float(np.median([e[m][0].elapsed_time(e[m][1]) for e in ev_list]))}
+                 for m in runs}
+    stats = {}
+    for mode, (r, flags) in runs.items():
+        r.check(data, mode)                      # what was timed
+        stats[mode] = r.stats_run(flags, waves)  # untimed
+        r.check(data, mode + " (stats run)")
+    comp = {m: runs[m][0].comp for m in runs}
+    n_blocks = runs["mrr"][0].blocks
+    for r, _ in runs.values():
+        r.close()
+    return wall, kernel_ms, comp, n_blocks, stats
+
+
+def side_leg(ctx, name: str, data: bytes, streams: dict, steps: int, warmup: int, waves: int,
+             copy_gbps: float | None) -> dict:
+    """Other configurations on the same GPU, each mode timed alone (`streams`:
+    mode name -> (stream bytes, flags))."""
+    size = len(data)
+    runs = {m: (StreamRun(ctx, s, size), f) for m, (s, f) in streams.items()}
+    ms = time_modes(runs, steps, warmup, waves)
+    res = {}
+    for m, (r, f) in runs.items():
+        r.check(data, f"{name} {m}")
+        st = r.stats_run(f, waves)
+        r.check(data, f"{name} {m} (stats run)")
+        res[m] = mode_entry(size, r.comp, ms[m], st, copy_gbps)
+        r.close()
+        log(f"{name} {m}: {res[m]['GBps']} GB/s ({res[m]['kernel_ms']} ms, ratio {res[m]['ratio']}, "
+            f"{res[m]['rounds_mean']} rounds/group)")
+    return res
+
+
+def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict:
+    """Speed against back-reference nesting depth (section "Performance Impact
+    of Nested back-references"): byte-level blocks of 1 MiB whose token
+    streams hold k interleaved chains of 16-byte back-references, each copying
+    the output of the one k sequences before it, so that every group of 64
+    sequences takes 64/k rounds of Multi-Round Resolution; Sequential Copying
+    of the same blocks beside it."""
+    import oracle
+    import synth
+    import paper_1606_00519_amd as gmp
+    res = {}
+    for k in (64, 32, 16, 8, 4, 2, 1):
+        n_seq = (1 << 20) // 17
+        seqs, lits = synth.nesting_tokens(n_seq, k, str_len=16)
+        blk = oracle.encode_byte_block(seqs, lits, oracle.CompressParams(format=1))
+        raw = len(lits) + int(seqs[:, 1].sum())
+        rc, want = oracle.decompress_block(blk)
+        assert rc == 0 and len(want) == raw
+        # one stream of `mib` copies of the block (block size = its raw length)
+        nb = max(1, (mib << 20) // raw)
+        s = oracle.assemble_stream([blk] * nb, raw, raw * nb)
+        data = want * nb
+        runs = {"mrr": (StreamRun(ctx, s, len(data)), gmp.MODE_MRR), "sc": (StreamRun(ctx, s, len(data)), gmp.MODE_SC)}
+        ms = time_modes(runs, max(3, steps // 2), warmup, waves)
+        e = {"depth": 64 // k, "blocks": nb, "raw_bytes": len(data)}
+        for m, (r, f) in runs.items():
+            r.check(data, f"nesting k={k} {m}")
+            st = r.stats_run(f, waves)
+            e[m] = {"GBps": round(len(data) / (ms[m]["mean"] / 1e3) / 1e9, 3), "kernel_ms": round(ms[m]["mean"], 4),
+                    "rounds_mean": st["rounds_mean"], "lz_us": st["phases"]["lz_us"],
+                    "bytes_per_round": st["bytes_per_round"][:4]}
+            r.close()
+        res[f"depth{64 // k}"] = e
+        log(f"nesting depth {64 // k}: MRR {e['mrr']['GBps']} GB/s ({e['mrr']['rounds_mean']} rounds), "
+            f"SC {e['sc']['GBps']} GB/s")
+    return res
 
 
 # ----------------------------------------------------------------------------- batched leg
@@ -305,6 +512,11 @@ def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads
 
     graph_ms = timed(lambda: db.batch.graph_launch())
     check("graph")
+    # the same launch shape without the graph and the device queue: one
+    # workgroup per job at the tuned wavefront count, then at one wavefront
+    db.out.zero_()
+    same_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=tun["waves"], persistent=False))
+    check("plain, tuned waves")
     db.out.zero_()
     plain_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=1, persistent=False))
     check("plain")
@@ -312,20 +524,26 @@ def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads
            "sub_block_kib": best_sub >> 10, "tuning": tun,
            "sample_ms_by_sub_block_kib": {k >> 10: round(v[0], 3) for k, v in sub_res.items()},
            "graph_ms": round(graph_ms, 3), "GBps": round(total / graph_ms / 1e6, 3),
-           "plain_ms": round(plain_ms, 3), "plain_GBps": round(total / plain_ms / 1e6, 3)}
+           "plain_same_waves_ms": round(same_ms, 3), "plain_same_waves_GBps": round(total / same_ms / 1e6, 3),
+           "plain_1wave_ms": round(plain_ms, 3), "plain_1wave_GBps": round(total / plain_ms / 1e6, 3)}
     db.batch.close()
-    log(f"batched: graph {graph_ms:.2f} ms ({res['GBps']} GB/s), plain {plain_ms:.2f} ms ({res['plain_GBps']} GB/s)")
+    log(f"batched: graph {graph_ms:.2f} ms ({res['GBps']} GB/s), plain at {tun['waves']} waves {same_ms:.2f} ms, "
+        f"plain at 1 wave {plain_ms:.2f} ms")
     return res
 
 
 # ----------------------------------------------------------------------------- serving leg
 def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threads: int, waves: int,
-              budget: int = 64 << 30):
+              budget: int = 64 << 30, level_seconds: float = 5.0):
     """Poisson arrivals of requests (log-uniform 64 KiB-64 MiB, text or CSV,
     ordinary or DE) at offered loads of 10-90 % of the batched peak, admitted
     by the library's request loop within an HBM budget; the requests' buffers
-    are resident on the device before the clock starts.  Reports achieved
-    GB/s, p50/p99 latency (completion - arrival) and admission wait."""
+    are resident on the device before the clock starts.  A request draws a
+    pooled input; a pool entry whose previous copy is still in flight (or not
+    yet checked) is not submitted again: the next free entry is taken.  Every
+    completed request's output is compared on the device with its source
+    bytes.  Reports achieved GB/s, p50/p99 latency (completion - arrival) and
+    admission wait per load level."""
     from concurrent.futures import ThreadPoolExecutor
 
     import torch
@@ -353,31 +571,66 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
     pool = []
     for raw, s in zip(raws, streams):
         nb = gmp.stream_info(s)[0]
-        pool.append({"d_in": torch.frombuffer(bytearray(s), dtype=torch.uint8).cuda(), "h": s,
+        pool.append({"d_in": torch.frombuffer(bytearray(s), dtype=torch.uint8).cuda(),
+                     "h": np.frombuffer(s, np.uint8),   # host headers, passed without a copy
+                     "ref": torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda(),
                      "out": torch.empty(len(raw), dtype=torch.uint8, device="cuda"),
-                     "status": torch.full((nb,), 99, dtype=torch.int32, device="cuda"), "raw": raw})
+                     "status": torch.full((nb,), 99, dtype=torch.int32, device="cuda"),
+                     "busy": False, "checked": None})
     torch.cuda.synchronize()
     mean_u = float(np.mean([len(r) for r in raws]))
     srv = gmp.Server(ctx, budget_bytes=budget, slots=4, waves=waves)
     rng = np.random.default_rng(synth.SERVE_SEED + 100)
+    stream = torch.cuda.current_stream()
     levels = []
-    for rho in (0.1, 0.3, 0.5, 0.7, 0.9):
+    bad = []          # device flags: an output that differs from its source, or a block status != 0
+    tag_entry = {}
+
+    def completed(cs):
+        for c in cs:
+            e = pool[tag_entry.pop(c["tag"])]
+            if c["status"] != 0:
+                raise RuntimeError(f"serve: request {c['tag']} ended with status {c['status']}")
+            bad.append(torch.ne(e["out"], e["ref"]).any() | torch.ne(e["status"], 0).any())
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            e["checked"] = ev
+            e["busy"] = False
+        return cs
+
+    def free_entry(k):
+        for j in range(n_pool):
+            e = pool[(k + j) % n_pool]
+            if not e["busy"] and (e["checked"] is None or e["checked"].query()):
+                return (k + j) % n_pool
+        return None
+
+    for rho in [round(0.1 * i, 1) for i in range(1, 10)]:
         lam = rho * peak_gbps * 1e9 / mean_u
-        arr = np.cumsum(rng.exponential(1.0 / lam, n_req))
-        which = rng.integers(0, n_pool, n_req)
+        n = int(min(n_req, max(200, level_seconds * lam)))
+        arr = np.cumsum(rng.exponential(1.0 / lam, n))
+        which = rng.integers(0, n_pool, n)
         done = []
+        late = 0
         t_start = time.perf_counter()
-        for i in range(n_req):
+        for i in range(n):
             while time.perf_counter() - t_start < arr[i]:
                 pass
-            e = pool[which[i]]
+            k = free_entry(int(which[i]))
+            while k is None:
+                done += completed(srv.poll(4096))
+                k = free_entry(int(which[i]))
+            late += (time.perf_counter() - t_start - arr[i]) > 1e-3
+            e = pool[k]
+            e["busy"] = True
+            tag_entry[i] = k
             srv.submit(e["d_in"], e["h"], e["out"], e["status"], gmp.MODE_AUTO, tag=i)
-            if i % 64 == 0:
-                done += srv.poll(4096)
+            if i % 16 == 0:
+                done += completed(srv.poll(4096))
         srv.drain(600000)
-        done += srv.poll(1 << 16)
-        if len(done) != n_req or any(c["status"] != 0 for c in done):
-            raise RuntimeError(f"serve: {len(done)} of {n_req} requests completed, or a request failed")
+        done += completed(srv.poll(1 << 16))
+        if len(done) != n:
+            raise RuntimeError(f"serve: {len(done)} of {n} requests completed")
         lat = np.array([(c["t_done_ns"] - c["t_submit_ns"]) / 1e6 for c in done])
         wait = np.array([(c["t_admit_ns"] - c["t_submit_ns"]) / 1e6 for c in done])
         span = (max(c["t_done_ns"] for c in done) - min(c["t_submit_ns"] for c in done)) / 1e9
@@ -385,18 +638,20 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
         lv = {"rho": rho, "offered_GBps": round(lam * mean_u / 1e9, 3), "achieved_GBps": round(byt / span / 1e9, 3),
               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
               "admit_wait_p50_ms": round(float(np.percentile(wait, 50)), 3),
-              "admit_wait_p99_ms": round(float(np.percentile(wait, 99)), 3), "requests": n_req}
+              "admit_wait_p99_ms": round(float(np.percentile(wait, 99)), 3), "requests": n,
+              "submitted_late_1ms": late}
         levels.append(lv)
         log(f"serve: rho {rho}: {lv}")
     info = srv.stats()
     srv.close()
     torch.cuda.synchronize()
-    for e in pool:
-        if not np.all(e["status"].cpu().numpy() == 0) or e["out"].cpu().numpy().tobytes() != e["raw"]:
-            raise RuntimeError("serve: a pooled request's output differs from its source bytes")
+    n_bad = int(torch.stack(bad).sum().item()) if bad else 0
+    if n_bad:
+        raise RuntimeError(f"serve: {n_bad} completed requests differ from their source bytes")
     return {"pool_requests": n_pool, "mean_request_bytes": int(mean_u), "budget_bytes": budget, "slots": 4,
             "launches": info["launches"], "peak_in_flight_bytes": info["peak_in_flight_bytes"],
-            "peak_concurrent_launches": info["peak_slots"],
+            "peak_concurrent_launches": info["peak_slots"], "checked_requests": len(bad),
+            "requests_per_level": f"min({n_req}, {level_seconds:g} s of arrivals)",
             "reference_peak_GBps": round(peak_gbps, 3), "levels": levels}
 
 
@@ -406,52 +661,73 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size-mib", type=int, default=256)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work for the oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU work for the oracle baseline, both of its legs together (0 = skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
                     help="decoder wavefronts per block (phase A); with 7, four of them resolve in phase B")
-    ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="serving: requests per load level (0 = skip)")
+    ap.add_argument("--legs", default="byte,csv,nesting,batched,serve",
+                    help="side legs beside the headline (comma-separated; '' = headline only)")
+    ap.add_argument("--csv-mib", type=int, default=1024, help="size of the low-entropy CSV configuration")
+    ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="serving: requests per load level (at most)")
     ap.add_argument("--serve-pool", type=int, default=192, help="serving: distinct device-resident requests")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one plain device-to-device copy of the output size (a reference kernel "
-                         "for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
               f"blocks are independent, see DESIGN.md for how the decoder would shard.", file=sys.stderr)
         return 2
+    legs = {x for x in args.legs.split(",") if x}
     size = args.size_mib << 20
     data, streams, baseline = oracle_leg(size, args.threads, args.cpu_seconds)
-    if args.copy_probe:
-        import torch
-        src = torch.empty(size, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # reads and writes exactly `size` bytes
-        torch.cuda.synchronize()
-        del src, dst
-    wall, kernel_ms, comp, n_blocks, phases = gpu_leg(data, streams, args.steps, args.warmup, args.waves)
-    batched = serving = None
-    if args.batch_items > 0 or args.serve_requests > 0:
-        import paper_1606_00519_amd as gmp
-        ctx = gmp.Context(0)
-        if args.batch_items > 0:
-            batched = batched_leg(ctx, data, args.batch_items, min(args.steps, 5), 1, args.threads)
-        if args.serve_requests > 0:
-            peak = batched["GBps"] if batched else size / (kernel_ms["mrr"] / 1e3) / 1e9
-            serving = serve_leg(ctx, data, peak, args.serve_pool, args.serve_requests, args.threads, args.waves)
-        ctx.close()
+    import paper_1606_00519_amd as gmp
+    import oracle
+    import synth
+    ctx = gmp.Context(0)
+    copy_ref = copy_reference(size, args.steps)
+    log(f"copy reference: {copy_ref['GBps']} GB/s")
+    wall, kernel_ms, comp, n_blocks, stats = gpu_leg(ctx, data, streams, args.steps, args.warmup, args.waves)
     raw_step = 2 * size
     ms_per_step = wall / args.steps * 1e3
     value = raw_step / (wall / args.steps) / 1e9
-    modes = {}
-    for m in ("mrr", "de"):
-        t = kernel_ms[m] / 1e3
-        modes[m] = {"GBps": round(size / t / 1e9, 3), "kernel_ms": round(kernel_ms[m], 4),
-                    "ratio": round(size / comp[m], 4), "compressed_bytes": comp[m],
-                    "hbm_frac": round((size + comp[m]) / t / 1e9 / HBM_PEAK_GBPS, 5), "phases": phases[m]}
+    modes = {m: mode_entry(size, comp[m], kernel_ms[m], stats[m], copy_ref["GBps"]) for m in ("mrr", "de")}
+    log(f"headline: {value:.2f} GB/s (MRR {modes['mrr']['GBps']}, DE {modes['de']['GBps']})")
+    side = {}
+    if "byte" in legs:
+        t0 = time.time()
+        bs = {}
+        for de in (0, 1):
+            p = oracle.CompressParams(block_size=1 << 20, window=32768, max_match=258, de=de, group=64, format=1)
+            bs[de] = oracle.compress(data, p, threads=args.threads)
+        log(f"byte: compressed in {time.time() - t0:.1f}s")
+        side["byte"] = side_leg(ctx, "byte", data, {"mrr": (bs[0], gmp.MODE_MRR), "de": (bs[1], gmp.MODE_DE),
+                                                    "sc": (bs[0], gmp.MODE_SC)},
+                                args.steps, args.warmup, args.waves, copy_ref["GBps"])
+        del bs
+    if "csv" in legs:
+        t0 = time.time()
+        n = args.csv_mib << 20
+        csv = synth.csv_rows(n, threads=args.threads).tobytes()
+        cs = {}
+        for de in (0, 1):
+            p = oracle.CompressParams(block_size=2 << 20, window=32768, max_match=258, lmax=12, sub_target_raw=32768,
+                                      de=de, group=64)
+            cs[de] = oracle.compress(csv, p, threads=args.threads)
+        log(f"csv: {n >> 20} MiB generated and compressed in {time.time() - t0:.1f}s")
+        side["csv"] = side_leg(ctx, "csv", csv, {"mrr": (cs[0], gmp.MODE_MRR), "de": (cs[1], gmp.MODE_DE)},
+                               max(5, args.steps // 2), args.warmup, args.waves, copy_ref["GBps"])
+        del csv, cs
+    if "nesting" in legs:
+        side["nesting"] = nesting_leg(ctx, args.steps, args.warmup, args.waves)
+    batched = serving = None
+    if "batched" in legs and args.batch_items > 0:
+        batched = batched_leg(ctx, data, args.batch_items, min(args.steps, 5), 1, args.threads)
+    if "serve" in legs and args.serve_requests > 0:
+        peak = batched["GBps"] if batched else size / (kernel_ms["mrr"]["mean"] / 1e3) / 1e9
+        serving = serve_leg(ctx, data, peak, args.serve_pool, args.serve_requests, args.threads, args.waves)
+    ctx.close()
     dom = max(modes, key=lambda m: modes[m]["kernel_ms"])
-    achieved = (size + comp[dom]) / (kernel_ms[dom] / 1e3) / 1e9
+    achieved = (size + comp[dom]) / (kernel_ms[dom]["mean"] / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -470,9 +746,12 @@ def main() -> int:
         "modes": modes,
         "roofline": {"bound": "hbm", "kernel": f"inflate_kernel ({dom})", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5),
-                     "traffic": traffic},
+                     "traffic": traffic, "copy_kernel_GBps": copy_ref["GBps"],
+                     "frac_of_copy": round(achieved / copy_ref["GBps"], 5)},
         "cpu_baseline": baseline,
+        "copy_reference": copy_ref,
     }
+    line.update(side)
     if batched:
         line["batched"] = batched
     if serving:

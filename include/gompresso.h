@@ -1,5 +1,6 @@
 /*
- * gompresso.h — C ABI of the MI355X (gfx950) Gompresso/Bit decompressor.
+ * gompresso.h — C ABI of the MI355X (gfx950) Gompresso decompressor: Gompresso/Bit
+ * (Huffman-coded sub-blocks) and Gompresso/Byte (byte-level records).
  *
  * Decompresses the block format of arXiv 1606.00519 (section "Gompresso
  * Overview"): independently compressed data blocks, each carrying two
@@ -24,6 +25,19 @@
  *   192 index: n_sub x {u32 bit_len, u32 n_seq, u32 n_lit, u32 raw_len}
  *   then u32 payload_bytes, 12 zero bytes, payload (sub-block bitstreams,
  *   each padded to 128 bits; sub-block i starts at 16*sum_{j<i} ceil(bit_len_j/128)).
+ * Byte-level block (Gompresso/Byte, sections "Parallel Compression" and
+ * "Parallel Decompression": the tokens are written with a direct byte-level
+ * encoding, no Huffman stage, and read straight from the block):
+ *   0   u32 magic 'GMPY'      4 u8 version(1)  5 u8 mode(0 ordinary, 1 DE)
+ *   6   u8 group G            7 u8 reserved(0)
+ *   8   u32 raw_len          12 u32 window (<= 32768)
+ *   16  u16 max_match (3..258)  18 u16 reserved(0)
+ *   20  u32 n_seq            24 u32 n_lit            28 u32 reserved(0)
+ *   32  n_seq records, u32 each: bits 0-7 literal length, 8-15 match length - 3,
+ *       16-31 distance (0: no back-reference, and then bits 8-15 are 0);
+ *       zero bytes to a multiple of 16; then the n_lit literal bytes, zero
+ *       bytes to a multiple of 16, and 16 more zero bytes.
+ *   Blocks of both formats may be mixed in one stream, batch or request.
  * Bit order and alphabets follow RFC 1951 (LSB-first packing, codes MSB-first,
  * length codes 257..285 and distance codes 0..29 with their extra bits);
  * symbol 256 ends every sub-block.
@@ -94,11 +108,14 @@ typedef int32_t gmp_status;
 typedef struct gmp_ctx gmp_ctx;
 typedef struct gmp_batch gmp_batch;
 
-/* Header fields of one block, parsed on the host. */
+/* Header fields of one block, parsed on the host.  format 0: Gompresso/Bit
+ * ('GMPB'); format 1: Gompresso/Byte ('GMPY', lmax = n_sub = 0). */
 typedef struct {
   uint32_t mode, group, lmax, raw_len, window, max_match;
   uint32_t n_sub, n_seq, n_lit, payload_bytes;
-  uint64_t block_bytes; /* header + index + payload */
+  uint64_t block_bytes; /* header + index + payload (Byte: header + records + literals) */
+  uint32_t format;
+  uint32_t reserved;
 } gmp_block_info;
 
 /* One block to decode.  The host fills n_seq / n_lit from gmp_block_info;
@@ -119,12 +136,15 @@ typedef struct {
   uint8_t* d_rounds;     /* optional, ceil(n_seq/64) bytes */
   uint64_t* d_times;     /* optional, 4 x uint64 */
   uint32_t* d_stats;     /* optional, GMP_STATS_WORDS x uint32 */
+  uint32_t format;       /* gmp_block_info.format: 1 (byte-level) needs no token workspace */
+  uint32_t reserved;
 } gmp_job;
 
 /* Counters of one block (gmp_job.d_stats, GMP_FLAG_STATS). */
 #define GMP_STATS_WORDS 80
 #define GMP_STAT_A2_PATH 0      /* how the Huffman stage ran: 1 segmented (the block's bits cut into equal
-                                   segments, one per decoder lane), 2 one lane per sub-block */
+                                   segments, one per decoder lane), 2 one lane per sub-block, 3 none
+                                   (a byte-level block) */
 #define GMP_STAT_REPAIRED 1     /* segmented: decoder lanes whose start had to be repaired */
 #define GMP_STAT_GROUPS 2       /* groups of 64 sequences */
 #define GMP_STAT_SPLIT 3        /* groups resolved in pieces (output larger than the on-chip window) */
@@ -164,7 +184,8 @@ gmp_status gmp_poll(gmp_ctx* ctx, void* stream, int32_t* h_first_error);
 /* Parse a block header from a host copy of at least its first 208 + 16*n_sub bytes
  * (len = bytes available).  Fails EFORMAT on bad magic/version/fields. */
 gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_block_info* out);
-/* Device token workspace one block needs, from its header's n_seq and n_lit: the
+/* Device token workspace one Gompresso/Bit block needs (a byte-level block needs
+ * none), from its header's n_seq and n_lit: the
  * token stream between the Huffman and the LZ77 stages (section "Gompresso
  * Overview": sequences and literal strings) plus the segmented decoder's
  * per-lane areas, which depend on the block's compressed bytes (comp_len).  Contexts, batches and servers allocate it themselves; a

@@ -1,4 +1,4 @@
-"""MI355X (gfx950) Gompresso/Bit decompressor — Python binding of the C ABI.
+"""MI355X (gfx950) Gompresso decompressor (Bit and Byte formats) — Python binding of the C ABI.
 
 Argument marshalling only: every decoding step runs in the HIP kernels of
 ``libgompresso_hip.so`` (built from ``csrc/`` by ``build.py``).  PyTorch
@@ -47,13 +47,15 @@ class GmpError(RuntimeError):
 
 class BlockInfo(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("mode", "group", "lmax", "raw_len", "window", "max_match", "n_sub",
-                                          "n_seq", "n_lit", "payload_bytes")] + [("block_bytes", C.c_uint64)]
+                                          "n_seq", "n_lit", "payload_bytes")] + [
+        ("block_bytes", C.c_uint64), ("format", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Job(C.Structure):
+    """gmp_job; `format` is the block's gmp_block_info format (1: byte-level, no token workspace)."""
     _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("d_out", C.c_void_p), ("out_len", C.c_uint64),
                 ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p),
-                ("d_stats", C.c_void_p)]
+                ("d_stats", C.c_void_p), ("format", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Request(C.Structure):
@@ -149,7 +151,7 @@ def block_info(h_block) -> dict:
     st = lib.gmp_block_info_parse(p, n, C.byref(info))
     if st:
         raise GmpError(st, "gmp_block_info_parse")
-    return {f: getattr(info, f) for f, _ in BlockInfo._fields_}
+    return {f: getattr(info, f) for f, _ in BlockInfo._fields_ if f != "reserved"}
 
 
 def workspace_bytes(n_seq: int, n_lit: int, comp_len: int) -> int:

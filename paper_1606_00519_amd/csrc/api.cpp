@@ -17,6 +17,8 @@
 namespace {
 
 constexpr uint32_t kMagicBlock = 0x42504D47u;   // 'GMPB'
+constexpr uint32_t kMagicByte = 0x59504D47u;    // 'GMPY'
+constexpr size_t kByteHdr = 32;
 constexpr uint32_t kMagicStream = 0x46504D47u;  // 'GMPF'
 constexpr size_t kHdrBytes = 192;
 constexpr size_t kIdxBytes = 16;
@@ -95,6 +97,28 @@ extern "C" const char* gmp_strerror(gmp_status s) {
 extern "C" gmp_status gmp_block_info_parse(const void* h_block, size_t len, gmp_block_info* out) {
   if (!h_block || !out) return GMP_EINVAL;
   const uint8_t* b = static_cast<const uint8_t*>(h_block);
+  if (len >= 4 && rd32(b) == kMagicByte) {
+    // Gompresso/Byte: header, records, literals
+    if (len < kByteHdr || b[4] != 1) return GMP_EFORMAT;
+    gmp_block_info i{};
+    i.format = 1;
+    i.mode = b[5];
+    i.group = b[6];
+    i.raw_len = rd32(b + 8);
+    i.window = rd32(b + 12);
+    i.max_match = rd16(b + 16);
+    i.n_seq = rd32(b + 20);
+    i.n_lit = rd32(b + 24);
+    if (i.mode > 1 || i.group < 1 || b[7] != 0 || i.window < 1 || i.window > 32768 || i.max_match < 3 ||
+        i.max_match > 258 || rd16(b + 18) != 0 || rd32(b + 28) != 0 || i.n_seq > 0x3FFFFFFFu)
+      return GMP_EFORMAT;
+    const uint64_t payload = ((4ull * i.n_seq + 15) & ~15ull) + (((uint64_t)i.n_lit + 15) & ~15ull) + 16;
+    if (payload > 0xFFFFFFFFull) return GMP_EFORMAT;
+    i.payload_bytes = (uint32_t)payload;
+    i.block_bytes = kByteHdr + payload;
+    *out = i;
+    return GMP_OK;
+  }
   if (len < kHdrBytes) return GMP_EFORMAT;
   if (rd32(b) != kMagicBlock || b[4] != 1) return GMP_EFORMAT;
   gmp_block_info i{};
@@ -254,7 +278,7 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
   if (out_len != info.raw_len) return GMP_ESIZE;
   if (!d_out && out_len) return GMP_EINVAL;
   HIP_OK(hipSetDevice(c->device));
-  const size_t ws = gmpk::workspace_bytes(info.n_seq, info.n_lit, block_len);
+  const size_t ws = gmpk::block_workspace_bytes(info.format, info.n_seq, info.n_lit, block_len);
   if ((st = ctx_reserve(c, 1, ws)) != GMP_OK) return st;
   gmpk::DevJob& j = c->h_jobs[0];
   j.comp = d_block;
@@ -296,7 +320,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     if (infos[b].block_bytes > offs[b + 1] - offs[b]) return GMP_EFORMAT;
     const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
     if (infos[b].raw_len != want) return GMP_ESIZE;
-    ws_total += gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit, offs[b + 1] - offs[b]);
+    ws_total += gmpk::block_workspace_bytes(infos[b].format, infos[b].n_seq, infos[b].n_lit, offs[b + 1] - offs[b]);
   }
   HIP_OK(hipSetDevice(c->device));
   if ((st = ctx_reserve(c, nb, ws_total)) != GMP_OK) return st;
@@ -308,7 +332,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     j.out = d_out + (uint64_t)b * bs;
     j.out_len = infos[b].raw_len;
     j.ws = c->d_ws + ws_off;
-    j.ws_len = gmpk::workspace_bytes(infos[b].n_seq, infos[b].n_lit, j.comp_len);
+    j.ws_len = gmpk::block_workspace_bytes(infos[b].format, infos[b].n_seq, infos[b].n_lit, j.comp_len);
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = d_status + b;
@@ -330,8 +354,8 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
   uint64_t ws_total = 0;
   for (uint32_t i = 0; i < n_jobs; i++) {
     const gmp_job& j = h_jobs[i];
-    if (!j.d_comp || !aligned16(j.d_comp) || (!j.d_out && j.out_len)) return GMP_EINVAL;
-    ws_total += gmpk::workspace_bytes(j.n_seq, j.n_lit, j.comp_len);
+    if (!j.d_comp || !aligned16(j.d_comp) || (!j.d_out && j.out_len) || j.format > 1) return GMP_EINVAL;
+    ws_total += gmpk::block_workspace_bytes(j.format, j.n_seq, j.n_lit, j.comp_len);
   }
   gmp_batch* b = new (std::nothrow) gmp_batch();
   if (!b) return GMP_ENOMEM;
@@ -360,7 +384,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     d.out = j.d_out;
     d.out_len = j.out_len;
     d.ws = b->d_ws + ws_off;
-    d.ws_len = gmpk::workspace_bytes(j.n_seq, j.n_lit, j.comp_len);
+    d.ws_len = gmpk::block_workspace_bytes(j.format, j.n_seq, j.n_lit, j.comp_len);
     d.rounds = j.d_rounds;
     d.times = j.d_times;
     d.status = d_status + i;

@@ -68,6 +68,13 @@ __host__ __device__ inline uint64_t workspace_bytes(uint32_t n_seq, uint32_t n_l
          (uint64_t)lanes * (8 * lane_cap_rec(n_seq, lanes) + lane_cap_lit(n_lit, comp_len, lanes) + kLaneExtra) + 256;
 }
 
+// Workspace of a block of either format: a byte-level block is resolved
+// straight from its records and literals and needs none.
+__host__ __device__ inline uint64_t block_workspace_bytes(uint32_t format, uint32_t n_seq, uint32_t n_lit,
+                                                          uint64_t comp_len) {
+  return format == 1 ? 0 : workspace_bytes(n_seq, n_lit, comp_len);
+}
+
 }  // namespace gmpk
 
 // d_first_err (may be null): set to the first non-zero block status of any launch

@@ -76,7 +76,9 @@ __device__ __forceinline__ void gstore16(GMEM uint8_t* p, uint4 v) {
 }
 __device__ __forceinline__ uint32_t gload32(const GMEM uint8_t* p) { return ((const GMEM Packed4*)p)->v; }
 
-constexpr uint32_t kMagicBlock = 0x42504D47u;  // 'GMPB'
+constexpr uint32_t kMagicBlock = 0x42504D47u;  // 'GMPB' (Gompresso/Bit)
+constexpr uint32_t kMagicByte = 0x59504D47u;   // 'GMPY' (Gompresso/Byte)
+constexpr uint32_t kByteHdr = 32;              // a byte-level block's header; its records follow
 constexpr uint32_t kHdrBytes = 192;
 constexpr uint32_t kIdxBytes = 16;
 constexpr uint32_t kNumLL = 286;
@@ -1217,17 +1219,23 @@ __device__ void coop_lits(uint32_t pos, uint32_t lsrc, uint32_t n, uint32_t* scr
 // baseline in its comparison of resolution strategies (one back-reference
 // after another, in sequence order).
 constexpr uint32_t kResMRR = 0, kResDE = 1, kResSC = 2;
+// Where phase B's sequence records come from: the packed token stream (8-byte
+// records, copied into LDS by DMA), the segmented decoder's lane areas, or
+// the 4-byte records of a byte-level block (both gathered by the fetcher).
+constexpr uint32_t kRecPacked = 0, kRecLanes = 1, kRecByte = 2;
 struct LzArgs {
-  const GMEM uint8_t* ws;  // token workspace: records, then literal bytes
-  uint64_t ws_len;
+  const GMEM uint8_t* recs;  // kRecPacked: 8-byte records; kRecByte: the block's 4-byte records
+  uint64_t recs_len;         // bytes readable at recs (bounds the DMA of kRecPacked)
+  const GMEM uint8_t* lits;  // the literal bytes, in sequence order
+  uint64_t lits_len;         // bytes readable at lits: at least n_lit + 16
+  uint32_t rec_src;          // kRecPacked, kRecLanes or kRecByte
   GMEM uint8_t* out;
   uint32_t n_seq, n_lit, raw_len;
   uint32_t res;      // kResMRR, kResDE (one pass) or kResSC (one back-reference at a time)
   bool verify_de;    // a DE group that breaks the DE rule is an error (it is resolved by rounds either way)
   bool stats;        // count bytes per round, split groups and DE groups resolved by rounds
   GMEM uint8_t* rounds;
-  // After segmented decoding the records are read from the lane areas
-  // (priv: the first area; null: from the packed stream in ws)
+  // kRecLanes: the segmented decoder's lane areas (priv: the first area)
   const GMEM uint8_t* priv;
   uint64_t lane_bytes, rep_off;  // an area's size, and where its repair records start
   uint32_t lanes;
@@ -1285,6 +1293,21 @@ struct StreamCursor {
   }
 };
 
+// A byte-level record (bits 0-7 literal length, 8-15 match length - 3, 16-31
+// distance, 0 for no back-reference) in the 8-byte form of the token stream.
+__device__ __forceinline__ uint64_t byte_record(uint32_t r) {
+  const uint32_t d = r >> 16, m = d ? ((r >> 8) & 0xFFu) + 3u : 0u;
+  return (uint64_t)(r & 0xFFu) | ((uint64_t)(m | (d << 16)) << 32);
+}
+// byte-level records o (even) and o + 1, with one 8-byte load (the record
+// area is padded to 16 bytes, so the load stays inside it)
+__device__ __forceinline__ void byte_record2(const LzArgs& a, uint32_t o, uint64_t& r0, uint64_t& r1) {
+  const GMEM uint64_t* p = (const GMEM uint64_t*)(a.recs + 4ull * o);
+  const uint64_t v = *p;
+  r0 = byte_record((uint32_t)v);
+  r1 = o + 1 < a.n_seq ? byte_record((uint32_t)(v >> 32)) : 0ull;
+}
+
 // Resolution runs as a pipeline over groups of 64 sequences.  Resolver
 // wavefront w takes groups w, w + kRes, w + 2 kRes, ...; everything a group
 // needs that does not depend on earlier groups' output (its records, the two
@@ -1309,10 +1332,9 @@ template <int kRes>
 __device__ void fetch_tokens(const LzArgs& a) {
   const uint32_t lane = lane_id();
   const uint32_t rec_chunks = (a.n_seq + 127) / 128, lit_chunks = (a.n_lit + 1023) / 1024;
-  const uint64_t lit_base = 8ull * a.n_seq;
   uint32_t rf = 0, lf = 0, tf = 0, carry_out = 0, carry_lit = 0;
   StreamCursor cur;
-  if (a.priv) cur.load(a, 0);
+  if (a.rec_src == kRecLanes) cur.load(a, 0);
   Spin sp;
   while (rf < rec_chunks || lf < lit_chunks) {
     uint32_t gmin = kDone;
@@ -1323,16 +1345,18 @@ __device__ void fetch_tokens(const LzArgs& a) {
     const uint32_t lit_cons = gmin < 2 * tf ? s_misc.g_lit[gmin % kGRing] : carry_lit;
     uint32_t issued = 0, gathered = 0;
     uint64_t g[8][2];
-    if (a.priv) {
-      // records gathered from the lane streams: lane l takes records 2l and
-      // 2l + 1 of up to eight 128-record chunks, loads first, stores after
+    if (a.rec_src != kRecPacked) {
+      // records gathered from the lane streams or the byte-level records:
+      // lane l takes records 2l and 2l + 1 of up to eight 128-record chunks,
+      // loads first, stores after
 #pragma unroll
       for (uint32_t c = 0; c < 8; c++) {
         const uint32_t ch = rf + c;
         if (ch < rec_chunks && 128ull * (ch + 1) <= 64ull * gmin + kRecRing && gathered == c) {
           const uint32_t o = 128 * ch + 2 * lane;
           if (o < a.n_seq) {
-            cur.record2(a, o, g[c][0], g[c][1]);
+            if (a.rec_src == kRecByte) byte_record2(a, o, g[c][0], g[c][1]);
+            else cur.record2(a, o, g[c][0], g[c][1]);
           } else {
             g[c][0] = g[c][1] = 0ull;
           }
@@ -1343,16 +1367,16 @@ __device__ void fetch_tokens(const LzArgs& a) {
     } else {
       while (rf < rec_chunks && 128ull * (rf + 1) <= 64ull * gmin + kRecRing && issued < 8) {
         uint64_t o = 1024ull * rf + 16 * lane;
-        if (o + 16 > a.ws_len) o = a.ws_len - 16;
-        dma16(a.ws + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
+        if (o + 16 > a.recs_len) o = a.recs_len - 16;
+        dma16(a.recs + o, &rec_ring()[128 * (rf % (kRecRing / 128))]);
         rf++;
         issued++;
       }
     }
     while (lf < lit_chunks && 1024ull * (lf + 1) <= (uint64_t)lit_cons + kLitRing && issued < 12) {
-      uint64_t o = lit_base + 1024ull * lf + 16 * lane;
-      if (o + 16 > a.ws_len) o = a.ws_len - 16;
-      dma16(a.ws + o, &lit_ring()[1024 * (lf % (kLitRing / 1024))]);
+      uint64_t o = 1024ull * lf + 16 * lane;
+      if (o + 16 > a.lits_len) o = a.lits_len - 16;
+      dma16(a.lits + o, &lit_ring()[1024 * (lf % (kLitRing / 1024))]);
       lf++;
       issued++;
     }
@@ -1425,7 +1449,7 @@ template <int kRes>
 __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
   uint8_t* ring = ring_ptr();
   const uint32_t lane = lane_id();
-  const GMEM uint8_t* lits = a.ws + 8ull * a.n_seq;
+  const GMEM uint8_t* lits = a.lits;
   uint32_t rec_avail = 0, lit_avail = 0;
   const uint32_t n_groups = (a.n_seq + 63) / 64;
   for (uint32_t g = w; g < n_groups; g += kRes) {
@@ -1926,6 +1950,143 @@ __device__ __forceinline__ void stamp(const DevJob& job, int i) {
   if (job.times && threadIdx.x == 0) gmem(job.times)[i] = wall_clock64();
 }
 
+// A3-A6 on the workgroup: the resolver wavefronts, the fetcher and the
+// flusher of the block's workgroup shape.  Called by every thread.
+template <int kDec>
+__device__ void resolve_phase(const LzArgs& a) {
+  Misc& sh = s_misc;
+  const uint32_t t = threadIdx.x, wave = t >> 6;
+  if (t == 0) {
+    sh.rec_avail = 0;
+    sh.lit_avail = 0;
+    sh.done_upto = 0;
+    sh.flushed = 0;
+  }
+  constexpr int kRes = resolver_waves<kDec>();
+  if (t < kMaxDecWaves) sh.next_group[t] = t < (uint32_t)kRes ? t : kDone;
+  __syncthreads();
+  if (wave == kDec) {
+    fetch_tokens<kRes>(a);
+  } else if (wave == flusher_wave<kDec>()) {
+    flush_output(a);
+  } else if (wave < (uint32_t)kRes) {
+    resolve_groups<kRes>(a, wave);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- Gompresso/Byte
+// Checks of a byte-level block's records before they are resolved, in the
+// order the CPU reference decoder checks them: first the totals against the
+// header (ESUB), then record by record, the first failing record deciding the
+// class: a match field without a distance (EFORMAT), a match longer than
+// max_match (ELEN), a distance beyond the window or reaching before the
+// block's start (EDIST).  The records are read in chunks of four per thread,
+// the output position of each from a workgroup prefix sum, with the next
+// chunk's load issued before the current one is checked.
+template <int kThreads>
+__device__ int check_byte_records(const GMEM uint8_t* recs, uint32_t n_seq, uint32_t n_lit, uint32_t raw_len,
+                                  uint32_t window, uint32_t max_match) {
+  const uint32_t t = threadIdx.x;
+  constexpr uint32_t kChunk = 4 * kThreads;
+  __shared__ unsigned long long s_first_bad;
+  if (t == 0) s_first_bad = ~0ull;
+  uint64_t out_carry = 0, lit_carry = 0, first_bad = ~0ull;
+  const uint32_t n_chunks = (n_seq + kChunk - 1) / kChunk;
+  // the record area is padded to 16 bytes: every 16-byte load starting below n_seq records stays inside it
+  auto load = [&](uint32_t c) -> uint4 {
+    const uint64_t i = (uint64_t)c * kChunk + 4ull * t;
+    return i < n_seq ? gload16(recs + 4 * i) : make_uint4(0u, 0u, 0u, 0u);
+  };
+  uint4 next = n_chunks ? load(0) : make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t c = 0; c < n_chunks; c++) {
+    const uint4 cur = next;
+    if (c + 1 < n_chunks) next = load(c + 1);
+    const uint32_t r[4] = {cur.x, cur.y, cur.z, cur.w};
+    const uint64_t i0 = (uint64_t)c * kChunk + 4ull * t;
+    uint32_t lit[4], m[4], sum_out = 0, sum_lit = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool valid = i0 + k < n_seq;
+      const uint32_t d = r[k] >> 16;
+      lit[k] = valid ? (r[k] & 0xFFu) : 0u;
+      m[k] = valid && d ? ((r[k] >> 8) & 0xFFu) + 3u : 0u;
+      sum_out += lit[k] + m[k];
+      sum_lit += lit[k];
+    }
+    uint32_t v[4] = {sum_out, sum_lit, 0u, 0u}, tot[4];
+    block_excl_scan4<kThreads>(v, tot);
+    uint64_t produced = out_carry + v[0];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool valid = i0 + k < n_seq;
+      const uint32_t d = r[k] >> 16, mf = (r[k] >> 8) & 0xFFu;
+      produced += lit[k];
+      const int cls = !valid ? kOK
+                      : (d == 0 && mf != 0) ? kEFORMAT
+                      : (m[k] > max_match) ? kELEN
+                      : (d && (d > window || d > produced)) ? kEDIST : kOK;
+      if (cls != kOK && first_bad == ~0ull) first_bad = ((i0 + k) << 8) | (uint64_t)(-cls);
+      produced += m[k];
+    }
+    out_carry += tot[0];
+    lit_carry += tot[1];
+  }
+  if (first_bad != ~0ull) atomicMin(&s_first_bad, (unsigned long long)first_bad);
+  __syncthreads();
+  if (lit_carry != n_lit || out_carry != raw_len) return kESUB;
+  return s_first_bad == ~0ull ? kOK : -(int)(s_first_bad & 0xFFu);
+}
+
+// A byte-level block (section "Parallel Decompression": its fixed-length
+// records are read straight from the compressed block, so decoding and LZ77
+// decompression are one pass): header checks, record checks, then A3-A6 with
+// the fetcher gathering the records from the block.
+template <int kDec, int kMode>
+__device__ int inflate_byte_block(const DevJob& job, uint32_t flags) {
+  constexpr uint32_t kThreads = block_threads<kDec>();
+  Misc& sh = s_misc;
+  const GMEM uint8_t* blk = gmem(job.comp);
+  if (job.comp_len < kByteHdr) return kEFORMAT;
+  const uint32_t w1 = ld32(blk + 4);
+  const uint32_t mode = (w1 >> 8) & 0xFF, group = (w1 >> 16) & 0xFF;
+  const uint32_t raw_len = ld32(blk + 8), window = ld32(blk + 12), w4 = ld32(blk + 16);
+  const uint32_t max_match = w4 & 0xFFFF, n_seq = ld32(blk + 20), n_lit = ld32(blk + 24);
+  if ((w1 & 0xFF) != 1 || mode > 1 || group < 1 || (w1 >> 24) != 0 || window < 1 || window > 32768 ||
+      max_match < 3 || max_match > 258 || (w4 >> 16) != 0 || ld32(blk + 28) != 0 || n_seq > 0x3FFFFFFFu)
+    return kEFORMAT;
+  const uint64_t rec_bytes = (4ull * n_seq + 15) & ~15ull, lit_bytes = (((uint64_t)n_lit + 15) & ~15ull) + 16;
+  if (kByteHdr + rec_bytes + lit_bytes > job.comp_len) return kEFORMAT;
+  if (n_seq != job.n_seq || n_lit != job.n_lit) return kEFORMAT;
+  if (raw_len != job.out_len) return kESIZE;
+  const bool de_ok = mode == 1 && (group % 64) == 0;
+  if (kMode == GMPK_MODE_DE && !de_ok) return kEINVAL;
+  const bool single_pass = (kMode == GMPK_MODE_DE) || (kMode == GMPK_MODE_AUTO && de_ok);
+  const int e = check_byte_records<kThreads>(blk + kByteHdr, n_seq, n_lit, raw_len, window, max_match);
+  if (e != kOK) return e;
+  if (threadIdx.x == 0) sh.a2_path = 3;
+  stamp(job, 1);
+  stamp(job, 2);
+  LzArgs a;
+  a.rec_src = kRecByte;
+  a.recs = blk + kByteHdr;
+  a.recs_len = rec_bytes;
+  a.lits = blk + kByteHdr + rec_bytes;
+  a.lits_len = lit_bytes;
+  a.out = gmem(job.out);
+  a.n_seq = n_seq;
+  a.n_lit = n_lit;
+  a.raw_len = raw_len;
+  a.res = kMode == GMPK_MODE_SC ? kResSC : (single_pass ? kResDE : kResMRR);
+  a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
+  a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
+  a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
+  a.priv = nullptr;
+  if (n_seq) resolve_phase<kDec>(a);
+  stamp(job, 3);
+  return sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
+}
+
 // Decodes one block and returns its status (the same value in every thread).
 // kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR,
 // GMPK_MODE_DE or GMPK_MODE_SC.
@@ -1946,6 +2107,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   if (t < 64) sh.rbytes[t] = 0;
   __syncthreads();
   const GMEM uint8_t* blk = gmem(job.comp);
+  if (job.comp_len >= 4 && ld32(blk) == kMagicByte) return inflate_byte_block<kDec, kMode>(job, flags);
   // ---- A0: header
   int err = kOK;
   uint32_t mode = 0, group = 0, lmax = 0, raw_len = 0, window = 0, max_match = 0, n_sub = 0, n_seq = 0,
@@ -2067,8 +2229,11 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   // ---- A3-A6: the decoder wavefronts resolve, the fetcher stages tokens,
   // the last wavefront writes the output
   LzArgs a;
-  a.ws = gmem(job.ws);
-  a.ws_len = job.ws_len;
+  a.rec_src = segmented ? kRecLanes : kRecPacked;
+  a.recs = gmem(job.ws);
+  a.recs_len = job.ws_len;
+  a.lits = gmem(job.ws) + 8ull * n_seq;
+  a.lits_len = job.ws_len - 8ull * n_seq;
   a.out = gmem(job.out);
   a.n_seq = n_seq;
   a.n_lit = n_lit;
@@ -2085,23 +2250,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     a.rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;
     a.lanes = kLanes;
   }
-  if (t == 0) {
-    sh.rec_avail = 0;
-    sh.lit_avail = 0;
-    sh.done_upto = 0;
-    sh.flushed = 0;
-  }
-  constexpr int kRes = resolver_waves<kDec>();
-  if (t < kMaxDecWaves) sh.next_group[t] = t < (uint32_t)kRes ? t : kDone;
-  __syncthreads();
-  if (wave == kDec) {
-    fetch_tokens<kRes>(a);
-  } else if (wave == flusher_wave<kDec>()) {
-    flush_output(a);
-  } else if (wave < (uint32_t)kRes) {
-    resolve_groups<kRes>(a, wave);
-  }
-  __syncthreads();
+  resolve_phase<kDec>(a);
   stamp(job, 3);
   return sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
 }

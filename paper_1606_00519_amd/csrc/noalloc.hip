@@ -50,7 +50,7 @@ extern "C" gmp_status gmp_decompress_block_noalloc(const uint8_t* d_block, size_
   if (info.block_bytes > block_len) return GMP_EFORMAT;
   if (out_len != info.raw_len) return GMP_ESIZE;
   if (!d_out && out_len) return GMP_EINVAL;
-  const uint64_t ws = gmpk::workspace_bytes(info.n_seq, info.n_lit, block_len);
+  const uint64_t ws = gmpk::block_workspace_bytes(info.format, info.n_seq, info.n_lit, block_len);
   if (ws > GMP_NOALLOC_SCRATCH_BYTES) return GMP_ERANGE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GMP_EDEVICE;

@@ -39,7 +39,6 @@
 namespace {
 
 constexpr uint32_t kMagicStream = 0x46504D47u;  // 'GMPF'
-constexpr uint32_t kMagicBlock = 0x42504D47u;   // 'GMPB'
 constexpr uint64_t kUnit = 256;
 
 uint64_t now_ns() {
@@ -368,12 +367,12 @@ extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
   rq.jobs.resize(nb);
   for (uint32_t b = 0; b < nb; b++) {
     const uint64_t o0 = rd64(hs + 32 + 8 * (size_t)b), o1 = rd64(hs + 32 + 8 * (size_t)b + 8);
-    if (o0 > o1 || o1 > req->len || (o0 & 15) || o1 - o0 < 192) return GMP_EFORMAT;
+    if (o0 > o1 || o1 > req->len || (o0 & 15) || o1 - o0 < 32) return GMP_EFORMAT;
     const uint8_t* blk = hs + o0;
-    if (rd32(blk) != kMagicBlock) return GMP_EFORMAT;
     gmp_block_info info;
     gmp_status st = gmp_block_info_parse(blk, o1 - o0, &info);
     if (st != GMP_OK) return st;
+    if (info.block_bytes > o1 - o0) return GMP_EFORMAT;
     const uint64_t want = (b + 1 < nb) ? bs : total - (uint64_t)b * bs;
     if (info.raw_len != want) return GMP_ESIZE;
     if (mode == GMP_MODE_DE && !(info.mode == 1 && info.group % 64 == 0)) return GMP_EINVAL;
@@ -383,7 +382,7 @@ extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
     j.out = req->d_out + (uint64_t)b * bs;
     j.out_len = info.raw_len;
     j.ws = nullptr;
-    j.ws_len = gmpk::workspace_bytes(info.n_seq, info.n_lit, o1 - o0);
+    j.ws_len = gmpk::block_workspace_bytes(info.format, info.n_seq, info.n_lit, o1 - o0);
     j.rounds = nullptr;
     j.times = nullptr;
     j.status = req->d_status + b;

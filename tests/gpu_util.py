@@ -80,7 +80,7 @@ def decode_batch(ctx, blocks: list[bytes], flags: int = 0, waves: int = 1, persi
     for k, (b, i) in enumerate(zip(blocks, infos)):
         jobs.append(gmp.Job(d_in.data_ptr() + offs[k], len(b), buf.data_ptr() + GUARD + outs[k], i["raw_len"],
                             i["n_seq"], i["n_lit"], rounds.data_ptr() + int(goff[k]) if stats else None, None,
-                            cnt.data_ptr() + 4 * gmp.STATS_WORDS * k if stats else None))
+                            cnt.data_ptr() + 4 * gmp.STATS_WORDS * k if stats else None, i["format"]))
     print(f"[gpu] decode_batch blocks={len(blocks)} flags={flags:#x} waves={waves} persistent={persistent}",
           flush=True)
     batch = ctx.batch_create(jobs, status)
@@ -126,7 +126,7 @@ def decode_stream_batched(ctx, stream: bytes, flags: int = 0, waves: int = 1, pe
         blk = stream[offs[b]:offs[b + 1]]
         info = gmp.block_info(blk)
         jobs.append(gmp.Job(d_in.data_ptr() + offs[b], len(blk), buf.data_ptr() + GUARD + b * bs, info["raw_len"],
-                            info["n_seq"], info["n_lit"], None))
+                            info["n_seq"], info["n_lit"], None, None, None, info["format"]))
     batch = ctx.batch_create(jobs, status)
     batch.run(flags, waves=waves, persistent=persistent)
     torch.cuda.synchronize()
