@@ -149,6 +149,10 @@ typedef struct {
 #define GMP_STAT_GROUPS 2       /* groups of 64 sequences */
 #define GMP_STAT_SPLIT 3        /* groups resolved in pieces (output larger than the on-chip window) */
 #define GMP_STAT_DE_ROUNDS 4    /* groups of a DE block that broke the DE rule and were resolved by rounds */
+#define GMP_STAT_STALL_SITE 5   /* 0, or (status GMP_ESTALL) the wait that ran out first: 1 Huffman-stage
+                                   fetcher, 2/3 a decoder lane's bit ring (segmented / one lane per
+                                   sub-block), 4 token fetcher, 5 output window, 6 staged records, 7 staged
+                                   literals, 8 resolution hand-over, 9 output flusher */
 #define GMP_STAT_ROUND_BYTES 16 /* [16 + r]: back-reference bytes copied in round r + 1, over all groups
                                    (r < 64): the numerator of the paper's bytes-per-round measure */
 

@@ -37,6 +37,7 @@ static_assert(sizeof(DevJob) == 96, "DevJob layout");
 //   [1] decoder lanes whose start was repaired (segmented decoding)
 //   [2] groups of 64 sequences, [3] groups resolved in window-sized pieces
 //   [4] groups of a DE block resolved by rounds because they break the DE rule
+//   [5] the wait that ran out first when the status is ESTALL (0: none)
 //   [16 + r] back-reference bytes copied in round r + 1 (r < 64), all groups
 constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 

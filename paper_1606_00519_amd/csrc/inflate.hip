@@ -224,7 +224,7 @@ struct Misc {
   // statistics (GMPK_FLAG_STATS with DevJob::stats): bytes copied per round,
   // groups resolved in pieces, DE groups resolved by rounds
   uint32_t rbytes[64];
-  uint32_t n_split, n_de_rounds, a2_path, n_repaired;
+  uint32_t n_split, n_de_rounds, a2_path, n_repaired, stall_site;
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
@@ -264,8 +264,16 @@ __device__ __forceinline__ void set_err(int e) { atomicCAS(&s_misc.err, 0, e); }
 // hand-over never comes near the bound; the bound only guarantees that a
 // fault in the hand-over logic ends the kernel instead of hanging it.
 constexpr uint64_t kSpinTicks = 100000000ull;
+// Which wait ran out first (the block's stall-site counter, GMPK_FLAG_STATS):
+// the Huffman-stage fetcher, a decoder lane's bit ring (segmented or one lane
+// per sub-block), the token fetcher, the output window, staged records,
+// staged literals, the resolution hand-over, the flusher.
+constexpr uint32_t kSiteBits = 1, kSiteRingSeg = 2, kSiteRingSub = 3, kSiteTokens = 4, kSiteWindow = 5,
+                   kSiteRecs = 6, kSiteLits = 7, kSiteDone = 8, kSiteFlush = 9;
 struct Spin {
   uint64_t t0 = 0;
+  uint32_t site;
+  __device__ explicit Spin(uint32_t s) : site(s) {}
   // one pause of a wait loop; false when the wait must end
   __device__ __forceinline__ bool pause() {
     if (__hip_atomic_load(&s_misc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
@@ -273,6 +281,7 @@ struct Spin {
     if (t0 == 0) {
       t0 = now;
     } else if (now - t0 > kSpinTicks) {
+      atomicCAS(&s_misc.stall_site, 0u, site);
       __hip_atomic_store(&s_misc.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return false;
     }
@@ -422,7 +431,7 @@ __device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
     woff[v] = s_misc.sub_woff[f + 64 * v];
     fetched[v] = 0;
   }
-  Spin sp;
+  Spin sp(kSiteBits);
   for (;;) {
     bool left = false, issued = false;
     uint32_t limit[kDec];
@@ -453,7 +462,7 @@ __device__ void fetch_bitstreams(const GMEM uint8_t* payload) {
         fetched[v] = limit[v];
         lds_release(&s_misc.avail[f + 64 * v], fetched[v]);
       }
-      sp = Spin();
+      sp = Spin(kSiteBits);
     } else if (!sp.pause()) {
       return;
     }
@@ -491,7 +500,7 @@ __device__ int decode_subblock(const SubBlock& sb, uint32_t L, uint32_t lmax, ui
   // word k of the lane's stream (zero past its end); waits for the fetcher when needed
   auto ring_word = [&](uint32_t k) -> uint32_t {
     if (k < nw && k >= avail) {
-      Spin sp;
+      Spin sp(kSiteRingSub);
       for (;;) {
         avail = lds_acquire(&s_misc.avail[L]);
         if (k < avail) break;
@@ -611,7 +620,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   uint32_t avail = 0;
   auto ring_word = [&](uint32_t k) -> uint32_t {
     if (k < nw && k >= avail) {
-      Spin sp;
+      Spin sp(kSiteRingSeg);
       for (;;) {
         avail = lds_acquire(&s_misc.avail[L]);
         if (k < avail) break;
@@ -1335,7 +1344,7 @@ __device__ void fetch_tokens(const LzArgs& a) {
   uint32_t rf = 0, lf = 0, tf = 0, carry_out = 0, carry_lit = 0;
   StreamCursor cur;
   if (a.rec_src == kRecLanes) cur.load(a, 0);
-  Spin sp;
+  Spin sp(kSiteTokens);
   while (rf < rec_chunks || lf < lit_chunks) {
     uint32_t gmin = kDone;
 #pragma unroll
@@ -1384,7 +1393,7 @@ __device__ void fetch_tokens(const LzArgs& a) {
       if (!sp.pause()) return;
       continue;
     }
-    sp = Spin();
+    sp = Spin(kSiteTokens);
     wait_all_memory();
 #pragma unroll
     for (uint32_t c = 0; c < 8; c++) {
@@ -1420,7 +1429,7 @@ __device__ void fetch_tokens(const LzArgs& a) {
 // Wait until output positions below `end` may be written (see above);
 // false if the wait was abandoned.
 __device__ __forceinline__ bool wait_window(uint32_t end) {
-  Spin sp;
+  Spin sp(kSiteWindow);
   for (uint32_t i = 0;; i++) {
     const uint32_t done = lds_acquire(&s_misc.done_upto), fl = lds_acquire(&s_misc.flushed);
     const uint32_t low = min(done > 32768u ? done - 32768u : 0u, fl);
@@ -1431,8 +1440,8 @@ __device__ __forceinline__ bool wait_window(uint32_t end) {
 // Wait until *p >= v; false if the wait was abandoned.  The first polls are
 // back to back: hand-overs between resolver wavefronts are on the critical
 // path and usually arrive within a few hundred cycles.
-__device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t v, uint32_t& seen) {
-  Spin sp;
+__device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t v, uint32_t& seen, uint32_t site) {
+  Spin sp(site);
   for (uint32_t i = 0;; i++) {
     seen = lds_acquire(p);
     if (seen >= v) return true;
@@ -1441,7 +1450,7 @@ __device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t v, uin
 }
 __device__ __forceinline__ bool wait_done(uint32_t pos) {
   uint32_t seen;
-  return wait_at_least(&s_misc.done_upto, pos, seen);
+  return wait_at_least(&s_misc.done_upto, pos, seen, kSiteDone);
 }
 
 // Resolver wavefront w of kRes.
@@ -1455,7 +1464,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
   for (uint32_t g = w; g < n_groups; g += kRes) {
     const uint32_t g0 = g * 64;
     const uint32_t need = min(a.n_seq, g0 + 64);
-    if (rec_avail < need && !wait_at_least(&s_misc.rec_avail, need, rec_avail)) break;
+    if (rec_avail < need && !wait_at_least(&s_misc.rec_avail, need, rec_avail, kSiteRecs)) break;
     const uint32_t j = g0 + lane;
     const bool valid = j < a.n_seq;
     const uint2 rec = valid ? rec_ring()[j % kRecRing] : make_uint2(0u, 0u);
@@ -1481,7 +1490,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
     // literals come from the LDS ring unless the group holds more than half of it
     const bool lits_staged = tot_lit <= kLitStagedMax;
     if (lits_staged && tot_lit && lit_avail < g_lit + tot_lit &&
-        !wait_at_least(&s_misc.lit_avail, g_lit + tot_lit, lit_avail))
+        !wait_at_least(&s_misc.lit_avail, g_lit + tot_lit, lit_avail, kSiteLits))
       break;
     uint32_t rounds = 0;
     bool split = false;
@@ -1593,7 +1602,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // resolved in pieces that fit the window, a literal run longer than the
       // window is streamed through it first
       if (!wait_done(g_out)) break;
-      uint32_t lo = 0;
+      uint32_t lo = 0, released = g_out;
       bool ok = true;
       while (ok && lo < m_cnt) {
         uint32_t base = readlane(pos, lo);
@@ -1683,12 +1692,16 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
           }
         }
         lds_release(&s_misc.done_upto, piece_end);
+        released = piece_end;
         lo = hi;
       }
       if (!ok) break;
-      // a dropped copy (bad distance) leaves its bytes unwritten: the group's
-      // output still ends at g_end, so the next group's wait ends
-      lds_release(&s_misc.done_upto, g_end);
+      // a dropped copy (bad distance) at the group's end leaves its bytes
+      // unwritten, so the last piece can end before g_end: the group's output
+      // still ends there.  Only then is g_end stored here; once a piece has
+      // published g_end the next group may already have moved done_upto on,
+      // and storing g_end again would move it back.
+      if (released != g_end) lds_release(&s_misc.done_upto, g_end);
       lds_release(&s_misc.next_group[w], g + kRes);
     }
     if (a.rounds && lane == 0) a.rounds[g] = (uint8_t)(min(rounds, 127u) | (split ? 0x80u : 0u));
@@ -1703,7 +1716,7 @@ __device__ void flush_output(const LzArgs& a) {
   const uint8_t* ring = ring_ptr();
   const uint32_t lane = lane_id();
   uint32_t fl = 0;
-  Spin sp;
+  Spin sp(kSiteFlush);
   while (fl < a.raw_len) {
     const uint32_t done = min(lds_acquire(&s_misc.done_upto), a.raw_len);
     const uint32_t end = done == a.raw_len ? done : (done & ~15u);
@@ -1711,7 +1724,7 @@ __device__ void flush_output(const LzArgs& a) {
       if (!sp.pause()) return;
       continue;
     }
-    sp = Spin();
+    sp = Spin(kSiteFlush);
     for (uint32_t p = fl + lane * 16; p < end; p += 1024) {
       if (p + 16 <= end) {
         uint4 v;
@@ -1801,7 +1814,8 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
     // the lane's bit ring starts at the row of the first bit it decodes
     g.base_word = (warm_start(g.p_begin, sub_of(g.p_begin, n_sub)) / 32) & ~3u;
-    g.n_words = min(pw, g.p_end / 32 + 8) - g.base_word;
+    // whole 16-byte rows: the fetcher moves rows, and the ring holds no partial one
+    g.n_words = min(pw, (g.p_end / 32 + 8 + 3) & ~3u) - g.base_word;
     g.cap_rec = (uint32_t)cap_rec;
     g.cap_lit = (uint32_t)cap_lit;
     g.rec_out = (GMEM uint64_t*)(priv + lane_bytes * t);
@@ -2103,6 +2117,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     sh.n_de_rounds = 0;
     sh.a2_path = 0;
     sh.n_repaired = 0;
+    sh.stall_site = 0;
   }
   if (t < 64) sh.rbytes[t] = 0;
   __syncthreads();
@@ -2275,6 +2290,7 @@ __device__ void run_block(const DevJob& job, uint32_t flags, int32_t* first_err)
       o[2] = (job.n_seq + 63) / 64;
       o[3] = s_misc.n_split;
       o[4] = s_misc.n_de_rounds;
+      o[5] = s_misc.stall_site;
     }
   }
   if (job.done) {

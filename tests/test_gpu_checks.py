@@ -240,3 +240,22 @@ def test_batched_items_up_to_4mib(ctx):
         st, outs, _ = decode_batch(ctx, blocks, waves=waves, persistent=persistent, workgroups=2)
         assert np.all(st == 0)
         assert outs == raws
+
+
+# --------------------------------------------------------------------------- hand-over order
+
+@pytest.mark.parametrize("waves", [2, 4, 7])
+def test_piecewise_group_keeps_done_mark_monotonic(ctx, waves):
+    # A first group larger than the on-chip span (32 KiB of literal runs, then
+    # 258-byte copies at distance 32768) is resolved in pieces; its last piece
+    # publishes the group's end, after which the next group, on another
+    # resolver wavefront, moves the finished-output mark on.  The piece-wise
+    # path must not store its end again afterwards: later groups would then
+    # wait on a mark that went backwards.  Repeated launches give the other
+    # wavefronts every chance to run ahead.
+    rng = np.random.default_rng(7)
+    data = rng.integers(0, 256, 32768, dtype=np.uint8).tobytes() * 6
+    blk = oracle.compress_block(data, P(block_size=1 << 18, sub_target_raw=4096))
+    st, outs, _ = decode_batch(ctx, [blk] * 64, waves=waves, runs=3)
+    assert np.all(st == 0)
+    assert all(o == data for o in outs)
