@@ -226,6 +226,10 @@ class StreamRun:
         rb = c[:, self.gmp.STAT_ROUND_BYTES:self.gmp.STAT_ROUND_BYTES + 64].sum(axis=0)
         last = int(np.max(np.nonzero(rb)[0])) + 1 if rb.any() else 0
         paths = np.bincount(c[:, self.gmp.STAT_A2_PATH], minlength=4)
+        rej = {}
+        for v in c[:, self.gmp.STAT_SEG_REJECT]:
+            if v:
+                rej[int(v)] = rej.get(int(v), 0) + 1
         return {"phases": {"tables_us": round(float(d[:, 0].mean()), 2),
                            "huffman_us": round(float(d[:, 1].mean()), 2),
                            "huffman_us_max": round(float(d[:, 1].max()), 2),
@@ -238,6 +242,8 @@ class StreamRun:
                 "round_bytes": [int(x) for x in rb[:last]],
                 "bytes_per_round": [round(float(x) / max(groups, 1), 3) for x in rb[:last]],
                 "a2_paths": {"segmented": int(paths[1]), "per_sub_block": int(paths[2]), "byte_level": int(paths[3])},
+                "segmented_rejections": rej,
+                "segmented_second_attempts": int(c[:, self.gmp.STAT_SEG_RETRY].sum()),
                 "repaired_lanes": int(c[:, self.gmp.STAT_REPAIRED].sum()),
                 "split_groups": int(c[:, self.gmp.STAT_SPLIT].sum())}
 
@@ -365,7 +371,8 @@ def side_leg(ctx, name: str, data: bytes, streams: dict, steps: int, warmup: int
         res[m] = mode_entry(size, r.comp, ms[m], st, copy_gbps)
         r.close()
         log(f"{name} {m}: {res[m]['GBps']} GB/s ({res[m]['kernel_ms']} ms, ratio {res[m]['ratio']}, "
-            f"{res[m]['rounds_mean']} rounds/group)")
+            f"{res[m]['rounds_mean']} rounds/group, phases {res[m]['phases']}, Huffman paths {res[m]['a2_paths']}, "
+            f"rejections {res[m]['segmented_rejections']})")
     return res
 
 
@@ -383,6 +390,12 @@ def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict
     for k in (64, 32, 16, 8, 4, 2, 1):
         n_seq = (1 << 20) // 17
         seqs, lits = synth.nesting_tokens(n_seq, k, str_len=16)
+        # a record holds at most 255 literals: the initial literal run of
+        # 1 + 17k bytes becomes literal-only records first (every group after
+        # the first still holds 64 consecutive links of the chains)
+        head, rest = divmod(int(seqs[0, 0]), 255)
+        seqs = np.concatenate([np.tile(np.array([[255, 0, 0]], np.uint32), (head, 1)),
+                               np.array([[rest, seqs[0, 1], seqs[0, 2]]], np.uint32), seqs[1:]])
         blk = oracle.encode_byte_block(seqs, lits, oracle.CompressParams(format=1))
         raw = len(lits) + int(seqs[:, 1].sum())
         rc, want = oracle.decompress_block(blk)
@@ -639,7 +652,7 @@ def serve_leg(ctx, text: bytes, peak_gbps: float, n_pool: int, n_req: int, threa
               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
               "admit_wait_p50_ms": round(float(np.percentile(wait, 50)), 3),
               "admit_wait_p99_ms": round(float(np.percentile(wait, 99)), 3), "requests": n,
-              "submitted_late_1ms": late}
+              "submitted_late_1ms": int(late)}
         levels.append(lv)
         log(f"serve: rho {rho}: {lv}")
     info = srv.stats()

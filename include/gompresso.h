@@ -153,6 +153,13 @@ typedef struct {
                                    fetcher, 2/3 a decoder lane's bit ring (segmented / one lane per
                                    sub-block), 4 token fetcher, 5 output window, 6 staged records, 7 staged
                                    literals, 8 resolution hand-over, 9 output flusher */
+#define GMP_STAT_SEG_REJECT 6   /* why segmented decoding was not accepted (then GMP_STAT_A2_PATH is 2), bits:
+                                   1 index, 2 invalid code in a lane, 4 a lane's area overflowed, 8 lanes did
+                                   not meet, 16 last lane's end, 32 open literal run, 64 per-sub-block counts,
+                                   128 repair failed; 0 when accepted or not attempted (after a second
+                                   attempt: the second attempt's reasons) */
+#define GMP_STAT_SEG_RETRY 7    /* 1: segmented decoding was attempted a second time, with a longer warm-up
+                                   before each segment, because lanes stayed out of step */
 #define GMP_STAT_ROUND_BYTES 16 /* [16 + r]: back-reference bytes copied in round r + 1, over all groups
                                    (r < 64): the numerator of the paper's bytes-per-round measure */
 

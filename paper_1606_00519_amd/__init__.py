@@ -30,8 +30,9 @@ FLAG_STATS = 0x100
 FLAG_VERIFY_DE = 0x200
 # per-block counters (gmp_job.d_stats)
 STATS_WORDS = 80
-STAT_A2_PATH, STAT_REPAIRED, STAT_GROUPS, STAT_SPLIT, STAT_DE_ROUNDS, STAT_STALL_SITE, STAT_ROUND_BYTES = (
-    0, 1, 2, 3, 4, 5, 16)
+(STAT_A2_PATH, STAT_REPAIRED, STAT_GROUPS, STAT_SPLIT, STAT_DE_ROUNDS, STAT_STALL_SITE, STAT_SEG_REJECT,
+ STAT_SEG_RETRY) = range(8)
+STAT_ROUND_BYTES = 16
 
 EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info",
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",

@@ -38,6 +38,8 @@ static_assert(sizeof(DevJob) == 96, "DevJob layout");
 //   [2] groups of 64 sequences, [3] groups resolved in window-sized pieces
 //   [4] groups of a DE block resolved by rounds because they break the DE rule
 //   [5] the wait that ran out first when the status is ESTALL (0: none)
+//   [6] why segmented decoding was not accepted (reason bits, 0: accepted)
+//   [7] 1 when segmented decoding was attempted a second time
 //   [16 + r] back-reference bytes copied in round r + 1 (r < 64), all groups
 constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 
@@ -47,10 +49,13 @@ constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 // slack; a lane that overflows makes the block fall back to one lane per
 // sub-block, which needs only the final area).
 constexpr uint32_t kPrivSlackRec = 64, kPrivSlackLit = 256;
-// per-lane extras of the segmented decoder: a log of its first symbol
-// boundaries, and room for the tokens of a repair of its start
-constexpr uint32_t kLogN = 128, kRepRec = 128, kRepLit = 512;
-constexpr uint32_t kLaneExtra = 4 * kLogN + 8 * kRepRec + kRepLit;
+// per-lane extra of the segmented decoder: a log of kLogN symbol boundaries
+// on its path from its entry, spread over its whole segment (the boundaries
+// logged are at least segment bits / kLogN apart, and never closer than
+// kLogGapMin).  The tokens of a repair of the lane's start go after the lane's
+// own tokens in its area.
+constexpr uint32_t kLogN = 128, kLogGapMin = 16;
+constexpr uint32_t kLaneExtra = 4 * kLogN;
 __host__ __device__ inline uint64_t final_bytes(uint32_t n_seq, uint32_t n_lit) { return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256; }
 __host__ __device__ inline uint64_t lane_cap_rec(uint32_t n_seq, uint32_t lanes) {
   return ((2ull * n_seq + lanes - 1) / lanes + kPrivSlackRec + 1) / 2 * 2;  // even: areas stay 16-byte aligned

@@ -97,6 +97,7 @@ constexpr uint32_t kTightPolls = 64;          // polls of a hand-over counter be
 constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
 constexpr uint32_t kSubMax = 512;             // most sub-blocks of a block decoded in segments
 constexpr uint32_t kOverlapBits = 768;        // bits a segment decoder reads ahead of its start to synchronise
+constexpr uint32_t kOverlapRetry = 8192;      // ... on a second attempt, when lanes stayed out of step
 constexpr uint32_t kSnapBits = 2048;          // segment boundaries this close to a sub-block's end move past it
 constexpr bool kSegmentedDecode = true;
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
@@ -224,11 +225,19 @@ struct Misc {
   // statistics (GMPK_FLAG_STATS with DevJob::stats): bytes copied per round,
   // groups resolved in pieces, DE groups resolved by rounds
   uint32_t rbytes[64];
-  uint32_t n_split, n_de_rounds, a2_path, n_repaired, stall_site;
+  uint32_t n_split, n_de_rounds, a2_path, n_repaired, stall_site, seg_reject, seg_retry;
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
-constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8, kSegRep = 16;
+constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8, kSegRep = 16, kSegOver = 32;
+// Why a block's segmented decoding was not accepted (bits of Seg::bad, the
+// block's GMPK_FLAG_STATS counter): an index entry out of line, a lane met an
+// invalid code, a lane's private area overflowed, a lane's entry is not the
+// previous lane's exit and the repair failed, the last lane did not end at
+// the payload's end, a literal run stayed open at a sub-block start, the
+// tokens counted per sub-block differ from the index.
+constexpr uint32_t kRejIndex = 1, kRejCode = 2, kRejOver = 4, kRejMeet = 8, kRejLast = 16, kRejRun = 32,
+                   kRejCount = 64, kRejRepair = 128;
 struct Seg {
   uint32_t sub_start[kSubMax + 1];  // first payload bit of each sub-block; [n_sub] = payload bits
   uint32_t sub_end[kSubMax];        // bit after each sub-block's end symbol
@@ -591,7 +600,9 @@ struct SegLane {
   uint32_t cap_rec, cap_lit;
   GMEM uint64_t* rec_out;
   GMEM uint8_t* lit_out;
-  GMEM uint32_t* log;           // the first kLogN literal/length symbol boundaries from the entry
+  GMEM uint32_t* log;           // literal/length symbol boundaries from the entry, >= log_gap bits apart
+  uint32_t log_gap;
+  uint32_t overlap;             // bits decoded without output before the segment, to get into step
 };
 
 // The sub-block holding payload bit p, and the first bit a lane whose segment
@@ -606,8 +617,8 @@ __device__ __forceinline__ uint32_t sub_of(uint32_t p, uint32_t n_sub) {
   }
   return lo;
 }
-__device__ __forceinline__ uint32_t warm_start(uint32_t p, uint32_t sb) {
-  return p >= s_seg.sub_start[sb] + kOverlapBits ? p - kOverlapBits : s_seg.sub_start[sb];
+__device__ __forceinline__ uint32_t warm_start(uint32_t p, uint32_t sb, uint32_t overlap) {
+  return p >= s_seg.sub_start[sb] + overlap ? p - overlap : s_seg.sub_start[sb];
 }
 
 template <int kDec>
@@ -670,7 +681,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
     s_misc.rd[L] = rd - 4;
   };
   uint32_t sb = sub_of(g.p_begin, n_sub);
-  uint32_t pos = warm_start(g.p_begin, sb);  // at most 3 words past base_word
+  uint32_t pos = warm_start(g.p_begin, sb, g.overlap);  // at most 3 words past base_word
   uint32_t sub_end = s_seg.sub_end[sb];
   uint32_t state = 0, n, kind, val;
   load(pos);
@@ -707,6 +718,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // per sub-block tallies: records and literals since the part's start (sc0,
   // lc0), and the match bytes of those records (mlen)
   uint32_t sc = 0, lc = 0, run = 0, plen = 0, sc0 = 0, lc0 = 0, mlen = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
+  uint32_t next_log = 0;  // the next boundary logged is the first at or after this bit
   // records leave two at a time (16 bytes; the area is 16-byte aligned): an
   // even-numbered record waits in rpend for the next one
   uint64_t rpend = 0;
@@ -714,6 +726,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // and log entries for the rest of theirs (lg0..lg2)
   uint32_t lw0 = 0, lw1 = 0, lw2 = 0, lg0 = 0, lg1 = 0, lg2 = 0;
   auto log_push = [&](uint32_t v) {
+    next_log = v + g.log_gap;
     const uint32_t wi = nlog & 3;
     if (wi == 3) {
       GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.log + (nlog & ~3u));
@@ -734,7 +747,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
     d->z = (uint32_t)r1;
     d->w = (uint32_t)(r1 >> 32);
   };
-  bool any_eob = false, fail = false;
+  bool any_eob = false, fail = false, over_hit = false;
   if (sb < n_sub && pos < g.p_end) {
     log_push(pos);
     for (;;) {
@@ -788,9 +801,10 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         run = gd ? 0u : run + (gl ? 1u : 0u);
         plen = (go & is_len) ? val : plen;
         state = (go & is_len) ? 1u : 0u;
-        if (go & (state == 0) & !is_end & (nlog < kLogN)) log_push(pos);
+        if (go & (state == 0) & !is_end & (nlog < kLogN) & (pos >= next_log)) log_push(pos);
         // one exit for both ends of the loop (fewer lane masks to track)
         fail = (bad & !nudge) | over;
+        over_hit |= over;
         if (fail | (go & (is_end | ((state == 0) & (pos >= g.p_end))))) break;
       }
       if (fail || !is_end) break;  // failed, or reached the segment's end inside sub-block sb
@@ -802,7 +816,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       uint32_t pseq = sc - sc0;
       if (run || !any_eob) {
         if (sc >= g.cap_rec) {
-          fail = true;
+          fail = over_hit = true;
           break;
         }
         if (sc & 1) store_pair(sc - 1, rpend, (uint64_t)run);
@@ -828,7 +842,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       if (sb >= n_sub || pos >= g.p_end) break;
       sub_end = s_seg.sub_end[sb];
       load(pos);
-      if (nlog < kLogN) log_push(pos);
+      if (nlog < kLogN && pos >= next_log) log_push(pos);
     }
     if (!fail && sb < n_sub && (sc - sc0 | lc - lc0)) {
       atomicAdd(&s_seg.cnt_seq[sb], sc - sc0);
@@ -849,7 +863,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   if ((nlog & 3) > 1) lgw[1] = lg1;
   if ((nlog & 3) > 2) lgw[2] = lg2;
   for (uint32_t i = lc & ~3u; i < lc; i++) g.lit_out[i] = (uint8_t)(lbuf >> (8 * (i & 3)));
-  if (fail) flags |= kSegFail;
+  if (fail) flags |= kSegFail | (over_hit ? kSegOver : 0u);
   if (sc == 0 && !any_eob) flags |= kSegPass;
   s_seg.entry[L] = entry;
   s_seg.exit_at[L] = fail ? kDone : pos;
@@ -904,14 +918,16 @@ struct SlowBits {
 };
 
 __device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const GMEM uint8_t* payload, uint32_t pw,
-                            uint32_t lmax,
-                            uint32_t window, uint32_t max_match, GMEM uint64_t* rep_rec_out,
-                            GMEM uint8_t* rep_lit_out) {
+                            uint32_t lmax, uint32_t window, uint32_t max_match) {
   const uint32_t lmask = (1u << lmax) - 1u;
+  // the repair's tokens go after the lane's own in its area
+  GMEM uint64_t* rep_rec_out = g.rec_out + s_seg.nrec[k];
+  GMEM uint8_t* rep_lit_out = g.lit_out + s_seg.nlit[k];
+  const uint32_t rep_rec_cap = g.cap_rec - s_seg.nrec[k], rep_lit_cap = g.cap_lit - s_seg.nlit[k];
   const uint32_t X = s_seg.exit_at[k - 1], E = s_seg.entry[k], sb = s_seg.entry_sub[k];
   const uint32_t nlog = s_seg.nlog[k];
   if (sb >= n_sub || nlog == 0 || X < s_seg.sub_start[sb] || X >= s_seg.sub_end[sb]) {
-    s_seg.bad = 1;
+    atomicOr(&s_seg.bad, kRejRepair);
     return;
   }
   const uint32_t sub_end = s_seg.sub_end[sb];
@@ -920,7 +936,9 @@ __device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const 
   uint32_t pos = X, state = 0, plen = 0, rsc = 0, rlc = 0, rraw = 0, run = 0, j = 0;
   uint32_t lg = g.log[0];
   bool met = false;
-  for (uint32_t it = 0; it < 4 * kLogN + 64; it++) {
+  // every step moves on by one symbol, and the walk ends once it is past the
+  // lane's last logged boundary
+  for (uint32_t it = 0; it < (1u << 20); it++) {
     if (state == 0) {
       while (j < nlog && lg < pos) {
         j++;
@@ -939,7 +957,7 @@ __device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const 
     const bool is_len = !is_dist && kind == kKindLen;
     const bool is_end = !is_dist && kind == kKindEnd;
     if (n == 0 || is_end || pos + n > sub_end || (is_dist && (plen > max_match || val > window))) break;
-    if ((is_dist && rsc >= kRepRec) || (is_lit && rlc >= kRepLit)) break;
+    if ((is_dist && rsc >= rep_rec_cap) || (is_lit && rlc >= rep_lit_cap)) break;
     if (is_dist) {
       rep_rec_out[rsc++] = (uint64_t)run | ((uint64_t)(plen | (val << 16)) << 32);
       rraw += plen;
@@ -955,13 +973,13 @@ __device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const 
     pos += n;
   }
   if (!met) {
-    s_seg.bad = 1;
+    atomicOr(&s_seg.bad, kRejRepair);
     return;
   }
   const uint32_t q = pos;
   // lane k's own path from its entry to q, under the same rules as its decoder
   uint32_t p2 = E, st2 = 0, pl2 = 0, sc = 0, lc = 0, raw = 0, run2 = 0;
-  for (uint32_t it = 0; p2 < q && it < 8 * kLogN + 1024; it++) {
+  for (uint32_t it = 0; p2 < q && it < q - E + 64; it++) {  // each step moves on by one bit or more
     uint32_t n, kind, val;
     b.peek(p2, st2, lmask, n, kind, val);
     const bool is_dist = st2 != 0;
@@ -993,7 +1011,7 @@ __device__ void repair_lane(const SegLane& g, uint32_t k, uint32_t n_sub, const 
     p2 = np;
   }
   if (p2 != q || st2 != 0) {
-    s_seg.bad = 1;
+    atomicOr(&s_seg.bad, kRejRepair);
     return;
   }
   atomicAdd(&s_seg.cnt_seq[sb], rsc - sc);
@@ -1246,7 +1264,7 @@ struct LzArgs {
   GMEM uint8_t* rounds;
   // kRecLanes: the segmented decoder's lane areas (priv: the first area)
   const GMEM uint8_t* priv;
-  uint64_t lane_bytes, rep_off;  // an area's size, and where its repair records start
+  uint64_t lane_bytes;  // an area's size
   uint32_t lanes;
 };
 
@@ -1257,10 +1275,11 @@ struct LzArgs {
 // parameters stay in registers while the lane's records come from one stream.
 struct StreamCursor {
   uint32_t s = 0, begin = 0, end = 0;  // stream s holds final records [begin, end)
-  uint32_t rs = 0, first = 0, drop = kDone, fix_rep = 0, fix_own = 0;
+  uint32_t rs = 0, first = 0, drop = kDone, fix_rep = 0, fix_own = 0, own = 0;
   const GMEM uint8_t* area = nullptr;
   __device__ __forceinline__ void load(const LzArgs& a, uint32_t k) {
     s = k;
+    own = s_seg.nrec[k];  // the lane's own records; its repair's records follow them
     begin = s_seg.entry[k];
     end = k + 1 < a.lanes ? s_seg.entry[k + 1] : a.n_seq;
     rs = s_seg.rep_rec[k];
@@ -1277,7 +1296,7 @@ struct StreamCursor {
     uint32_t x = first + (j - rs);
     x += (drop != kDone && x >= drop) ? 1u : 0u;
     const bool rep = j < rs;
-    const uint64_t off = rep ? a.rep_off + 8ull * j : 8ull * x;
+    const uint64_t off = rep ? 8ull * (own + j) : 8ull * x;
     const uint32_t fix = rep ? (j == 0 ? fix_rep : 0u) : (x == first ? fix_own : 0u);
     const uint64_t r = *(const GMEM uint64_t*)(area + off);
     return (r & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)r + fix);
@@ -1759,7 +1778,8 @@ __device__ __forceinline__ uint32_t snap_boundary(uint32_t p, uint32_t n_sub) {
 template <int kDec>
 __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, const GMEM uint8_t* payload_bytes,
                                  uint32_t n_sub, uint32_t n_seq, uint32_t n_lit, uint32_t payload, uint32_t lmax,
-                                 uint32_t window, uint32_t max_match, GMEM uint64_t* ws_seq, GMEM uint8_t* ws_lit) {
+                                 uint32_t window, uint32_t max_match, GMEM uint64_t* ws_seq, GMEM uint8_t* ws_lit,
+                                 uint32_t overlap) {
   constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
@@ -1788,7 +1808,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     block_excl_scan4<kThreads>(v, tot);
     const uint32_t word_off = carry[0] + v[0];
     if (s < n_sub) {
-      if (bit_len == 0 || (uint64_t)word_off + nwords > pw) s_seg.bad = 1;
+      if (bit_len == 0 || (uint64_t)word_off + nwords > pw) atomicOr(&s_seg.bad, kRejIndex);
       s_seg.sub_start[s] = 32 * word_off;
       s_seg.sub_end[s] = 32 * word_off + bit_len;
       s_seg.cnt_seq[s] = 0;
@@ -1800,10 +1820,13 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   if (t == 0) {
     s_seg.sub_start[n_sub] = 32 * pw;
-    if (carry[0] != pw || carry[1] != n_seq || carry[2] != n_lit) s_seg.bad = 1;
+    if (carry[0] != pw || carry[1] != n_seq || carry[2] != n_lit) atomicOr(&s_seg.bad, kRejIndex);
   }
   __syncthreads();
-  if (s_seg.bad) return false;
+  if (s_seg.bad) {
+    if (t == 0) sh.seg_reject = s_seg.bad;
+    return false;
+  }
   // segments: equal runs of 16-byte rows; each lane fetches from where its
   // warm-up may start to a little past its segment's end
   GMEM uint8_t* priv = gmem(job.ws) + fin;
@@ -1813,7 +1836,8 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.p_begin = snap_boundary(128 * (uint32_t)((uint64_t)rows * t / kLanes), n_sub);
     g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
     // the lane's bit ring starts at the row of the first bit it decodes
-    g.base_word = (warm_start(g.p_begin, sub_of(g.p_begin, n_sub)) / 32) & ~3u;
+    g.overlap = overlap;
+    g.base_word = (warm_start(g.p_begin, sub_of(g.p_begin, n_sub), overlap) / 32) & ~3u;
     // whole 16-byte rows: the fetcher moves rows, and the ring holds no partial one
     g.n_words = min(pw, (g.p_end / 32 + 8 + 3) & ~3u) - g.base_word;
     g.cap_rec = (uint32_t)cap_rec;
@@ -1821,6 +1845,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.rec_out = (GMEM uint64_t*)(priv + lane_bytes * t);
     g.lit_out = priv + lane_bytes * t + 8 * cap_rec;
     g.log = (GMEM uint32_t*)(g.lit_out + cap_lit);
+    g.log_gap = max(kLogGapMin, (g.p_end - g.p_begin + kLogN - 1) / kLogN);
     sh.sub_woff[t] = g.base_word;
     sh.sub_nw[t] = g.n_words;
     sh.rd[t] = 0;
@@ -1835,14 +1860,10 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   __syncthreads();
   // lanes whose entry is not the previous lane's exit: repair their start
-  GMEM uint64_t* rep_rec_out = nullptr;
-  GMEM uint8_t* rep_lit_out = nullptr;
   if (t < kLanes) {
-    rep_rec_out = (GMEM uint64_t*)(g.log + kLogN);
-    rep_lit_out = (GMEM uint8_t*)(rep_rec_out + kRepRec);
     if (t > 0 && !(s_seg.flags[t] & kSegFail) && !(s_seg.flags[t - 1] & kSegFail) &&
         s_seg.entry[t] != s_seg.exit_at[t - 1])
-      repair_lane(g, t, n_sub, payload_bytes, pw, lmax, window, max_match, rep_rec_out, rep_lit_out);
+      repair_lane(g, t, n_sub, payload_bytes, pw, lmax, window, max_match);
   }
   __syncthreads();
   // Each lane's effective token stream: its repair's tokens (if any), then its
@@ -1864,7 +1885,9 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     const uint32_t start = (flags & kSegRep) ? s_seg.exit_at[t - 1] : s_seg.entry[t];
     mid = eb < n_sub && start != s_seg.sub_start[eb];
     const bool meets = t == 0 ? s_seg.entry[0] == 0u : ((flags & kSegRep) || s_seg.entry[t] == s_seg.exit_at[t - 1]);
-    if ((flags & kSegFail) || !meets || (t + 1 == kLanes && s_seg.exit_at[t] != 32 * pw)) s_seg.bad = 1;
+    if (flags & kSegFail) atomicOr(&s_seg.bad, (flags & kSegOver) ? kRejOver : kRejCode);
+    if (!meets) atomicOr(&s_seg.bad, kRejMeet);
+    if (t + 1 == kLanes && s_seg.exit_at[t] != 32 * pw) atomicOr(&s_seg.bad, kRejLast);
   }
   __syncthreads();
   uint32_t carry_in = 0, own_fix = 0, drop = kDone;
@@ -1875,7 +1898,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
         if (s_seg.rep_rec[j] + s_seg.nrec[j] - s_seg.skip_rec[j] != 0) break;  // j has a sequence: the run starts there
       }
     } else if (t && s_seg.eff_tail[t - 1]) {
-      s_seg.bad = 1;  // an open literal run must continue in the next lane
+      atomicOr(&s_seg.bad, kRejRun);  // an open literal run must continue in the next lane
     }
     own_fix = (rsc ? 0u : carry_in) + s_seg.rep_run[t] - s_seg.skip_run[t];
     if (flags & kSegMaybe) {
@@ -1887,10 +1910,13 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   __syncthreads();
   for (uint32_t s = t; s < n_sub; s += kThreads) {
     const uint4 e = gload16(idx + kIdxBytes * s);
-    if (s_seg.cnt_seq[s] != e.y || s_seg.cnt_lit[s] != e.z || s_seg.cnt_raw[s] != e.w) s_seg.bad = 1;
+    if (s_seg.cnt_seq[s] != e.y || s_seg.cnt_lit[s] != e.z || s_seg.cnt_raw[s] != e.w) atomicOr(&s_seg.bad, kRejCount);
   }
   __syncthreads();
-  if (s_seg.bad) return false;
+  if (s_seg.bad) {
+    if (t == 0) sh.seg_reject = s_seg.bad;
+    return false;
+  }
   // pack the effective streams into the final token stream
   uint32_t v[4] = {0, 0, 0, 0}, tot[4];
   if (t < kLanes) {
@@ -1923,8 +1949,6 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     }
     return lo;
   };
-  const uint64_t rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;  // a lane area's repair records
-  const uint64_t rep_lit_off = rep_off + 8 * kRepRec;  // a lane area's repair literals
   for (uint32_t o = 16 * t; o < n_lit; o += 16 * kThreads) {
     const uint32_t n = min(16u, n_lit - o);
     uint32_t s = stream_of(s_seg.exit_at, o);
@@ -1941,7 +1965,8 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
         while (s + 1 < kLanes && s_seg.exit_at[s + 1] <= ok) s++;
         const uint32_t j = ok - s_seg.exit_at[s], rj = s_seg.rep_lit[s];
         const GMEM uint8_t* area = priv + lane_bytes * s;
-        const uint8_t b = j < rj ? area[rep_lit_off + j] : area[8 * cap_rec + s_seg.skip_lit[s] + (j - rj)];
+        // the repair's literals follow the lane's own
+        const uint8_t b = j < rj ? area[8 * cap_rec + s_seg.nlit[s] + j] : area[8 * cap_rec + s_seg.skip_lit[s] + (j - rj)];
         w[k / 4] |= (uint32_t)b << (8 * (k % 4));
       }
       q = make_uint4(w[0], w[1], w[2], w[3]);
@@ -2118,6 +2143,8 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     sh.a2_path = 0;
     sh.n_repaired = 0;
     sh.stall_site = 0;
+    sh.seg_reject = 0;
+    sh.seg_retry = 0;
   }
   if (t < 64) sh.rbytes[t] = 0;
   __syncthreads();
@@ -2181,8 +2208,18 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   const GMEM uint8_t* payload_bytes = blk + kHdrBytes + kIdxBytes * n_sub + 16;
   GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
   GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
-  const bool segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
-                                                max_match, ws_seq, ws_lit);
+  bool segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
+                                          max_match, ws_seq, ws_lit, kOverlapBits);
+  // Lanes that stayed out of step past what their repair covers (codes that
+  // fall into step slowly): a second attempt with a far longer warm-up costs
+  // less than decoding every sub-block in one lane.
+  __syncthreads();  // the rejection reasons are in LDS for every thread
+  if (!segmented && (sh.seg_reject & (kRejMeet | kRejRepair)) && !(sh.seg_reject & (kRejIndex | kRejCode)) &&
+      !sh.abort) {
+    if (t == 0) sh.seg_retry = 1;
+    segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
+                                       max_match, ws_seq, ws_lit, kOverlapRetry);
+  }
   uint32_t carry[4] = {0, 0, 0, 0};
   for (uint32_t c = 0; !segmented && c < n_sub; c += kLanes) {
     const uint32_t s = c + t;
@@ -2262,7 +2299,6 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, job.comp_len, kLanes);
     a.priv = gmem(job.ws) + final_bytes(n_seq, n_lit);
     a.lane_bytes = 8 * cap_rec + cap_lit + kLaneExtra;
-    a.rep_off = 8 * cap_rec + cap_lit + 4 * kLogN;
     a.lanes = kLanes;
   }
   resolve_phase<kDec>(a);
@@ -2291,6 +2327,8 @@ __device__ void run_block(const DevJob& job, uint32_t flags, int32_t* first_err)
       o[3] = s_misc.n_split;
       o[4] = s_misc.n_de_rounds;
       o[5] = s_misc.stall_site;
+      o[6] = s_misc.seg_reject;
+      o[7] = s_misc.seg_retry;
     }
   }
   if (job.done) {

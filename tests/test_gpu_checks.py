@@ -259,3 +259,24 @@ def test_piecewise_group_keeps_done_mark_monotonic(ctx, waves):
     st, outs, _ = decode_batch(ctx, [blk] * 64, waves=waves, runs=3)
     assert np.all(st == 0)
     assert all(o == data for o in outs)
+
+
+def test_slow_sync_blocks_decode_in_segments(ctx):
+    # DE streams of the CSV rows hold codes that fall into step slowly: in
+    # these 2 MiB blocks some decoder lanes (of 448) stay out of step for
+    # 6-8 kbit past their segment's start.  Each lane's boundary log spans its
+    # whole segment and a repair's tokens go after the lane's own, so the
+    # repair from the previous lane's exit covers them and the blocks are
+    # decoded in segments.
+    n = 2 << 20
+    blocks, raws = [], []
+    for b in (47, 55):
+        raw = synth.csv_rows(n, b * n).tobytes()
+        blocks.append(oracle.compress_block(raw, P(block_size=n, sub_target_raw=32768, de=1)))
+        raws.append(raw)
+    cnt = []
+    st, outs, _ = decode_batch(ctx, blocks, stats=True, waves=7, counters=cnt)
+    assert np.all(st == 0) and outs == raws
+    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, second attempts {[int(c[7]) for c in cnt]}, "
+          f"rejections {[int(c[6]) for c in cnt]}", flush=True)
+    assert all(c[0] == 1 for c in cnt)
