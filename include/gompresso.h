@@ -160,6 +160,8 @@ typedef struct {
                                    attempt: the second attempt's reasons) */
 #define GMP_STAT_SEG_RETRY 7    /* 1: segmented decoding was attempted a second time, with a longer warm-up
                                    before each segment, because lanes stayed out of step */
+#define GMP_STAT_SPILLED 8      /* back-references the decoding launch left to later launches
+                                   (gmp_tuning.rounds_per_launch) */
 #define GMP_STAT_ROUND_BYTES 16 /* [16 + r]: back-reference bytes copied in round r + 1, over all groups
                                    (r < 64): the numerator of the paper's bytes-per-round measure */
 
@@ -173,7 +175,15 @@ typedef struct {
                                decoders resolve and the seventh flushes */
   uint32_t persistent;      /* 1: persistent workgroups pull blocks from a device queue; 0: one workgroup per block */
   uint32_t workgroups;      /* persistent grid size (0 = one per compute unit) */
-  uint32_t reserved;
+  uint32_t rounds_per_launch; /* Multi-Round Resolution over several launches (the variant of section
+                               "Performance Impact of Nested back-references" that writes unresolved
+                               back-references to device memory for later kernels): 0 = every round in the
+                               decoding launch; R in 1..64 = at most R rounds per group of 64 sequences there,
+                               the back-references still pending (and those reading their bytes) go to a
+                               per-block list in device memory, which later launches resolve R rounds per 64
+                               entries at a time, ceil(64 / R) - 1 of them, then one launch finishes the
+                               list.  MRR blocks only (DE and Sequential Copying ignore it); batches only.
+                               The batch allocates the lists (16 bytes per sequence) on first use */
 } gmp_tuning;
 
 /* ---- context ------------------------------------------------------------------ */
@@ -273,7 +283,9 @@ gmp_status gmp_batch_graph_launch(gmp_ctx* ctx, gmp_batch* batch, void* stream);
 /* Choose launch parameters for a batch by timing candidates on the device
  * (section "Dependency on Data Block Size": parallelism per block against
  * per-block overheads): wavefronts per block in {1, 2, 4, 7} x {one workgroup per
- * job, persistent with one or two workgroups per compute unit}.  Each candidate
+ * job, persistent with one or two workgroups per compute unit}, all rounds in
+ * one launch; then, on the winning shape, rounds per launch in {1, 4, 16}
+ * (section "Performance Impact of Nested back-references").  Each candidate
  * runs once untimed, then `reps` (1..64) timed runs on `stream`; the least
  * median wins.  The batch's outputs are overwritten (with the same bytes, for
  * valid input).  *best receives the winner, *best_ms (may be NULL) its median

@@ -31,7 +31,7 @@ FLAG_VERIFY_DE = 0x200
 # per-block counters (gmp_job.d_stats)
 STATS_WORDS = 80
 (STAT_A2_PATH, STAT_REPAIRED, STAT_GROUPS, STAT_SPLIT, STAT_DE_ROUNDS, STAT_STALL_SITE, STAT_SEG_REJECT,
- STAT_SEG_RETRY) = range(8)
+ STAT_SEG_RETRY, STAT_SPILLED) = range(9)
 STAT_ROUND_BYTES = 16
 
 EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info",
@@ -79,7 +79,7 @@ class ServerInfo(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("persistent", C.c_uint32), ("workgroups", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("rounds_per_launch", C.c_uint32)]
 
 
 def _load():
@@ -189,16 +189,16 @@ class Batch:
         self.handle = h
 
     def run(self, flags: int = MODE_AUTO, waves: int = 1, persistent: bool = False, workgroups: int = 0,
-            stream=None) -> None:
-        t = Tuning(waves, int(persistent), workgroups, 0)
+            stream=None, rounds_per_launch: int = 0) -> None:
+        t = Tuning(waves, int(persistent), workgroups, rounds_per_launch)
         st = lib.gmp_batch_run(self.ctx.handle, self.handle, flags, C.byref(t), _stream_handle(stream))
         if st:
             raise GmpError(st, "gmp_batch_run")
 
     def graph_create(self, flags: int = MODE_AUTO, waves: int = 1, persistent: bool = True,
-                     workgroups: int = 0) -> None:
+                     workgroups: int = 0, rounds_per_launch: int = 0) -> None:
         """Capture this batch's launch as a HIP graph (gmp_batch_graph_create)."""
-        t = Tuning(waves, int(persistent), workgroups, 0)
+        t = Tuning(waves, int(persistent), workgroups, rounds_per_launch)
         st = lib.gmp_batch_graph_create(self.ctx.handle, self.handle, flags, C.byref(t))
         if st:
             raise GmpError(st, "gmp_batch_graph_create")
@@ -215,8 +215,8 @@ class Batch:
                               _stream_handle(stream))
         if st:
             raise GmpError(st, "gmp_autotune")
-        return ({"waves": t.waves_per_block, "persistent": bool(t.persistent), "workgroups": t.workgroups},
-                float(ms.value))
+        return ({"waves": t.waves_per_block, "persistent": bool(t.persistent), "workgroups": t.workgroups,
+                 "rounds_per_launch": t.rounds_per_launch}, float(ms.value))
 
     def close(self) -> None:
         if getattr(self, "handle", None):

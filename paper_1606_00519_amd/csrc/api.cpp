@@ -65,6 +65,8 @@ struct gmp_batch {
   int device = 0;
   uint32_t n = 0;
   gmpk::DevJob* d_jobs = nullptr;
+  std::vector<gmpk::DevJob> h_jobs;  // host copy of the job table (spill areas are added to it on first use)
+  uint8_t* d_spill = nullptr;        // spill lists of multi-launch resolution (allocated on first use)
   uint8_t* d_ws = nullptr;
   uint32_t* d_queue = nullptr;
   int32_t* d_first_err = nullptr;  // the context's first-error word
@@ -294,6 +296,7 @@ extern "C" gmp_status gmp_decompress_block(gmp_ctx* c, const uint8_t* d_block, s
   j.done = nullptr;
   j.n_seq = info.n_seq;
   j.n_lit = info.n_lit;
+  j.spill = nullptr;
   return ctx_launch(c, 1, flags, static_cast<hipStream_t>(stream));
 }
 
@@ -340,6 +343,7 @@ extern "C" gmp_status gmp_decompress_stream(gmp_ctx* c, const uint8_t* d_stream,
     j.done = nullptr;
     j.n_seq = infos[b].n_seq;
     j.n_lit = infos[b].n_lit;
+    j.spill = nullptr;
     ws_off += j.ws_len;
   }
   return ctx_launch(c, nb, flags, static_cast<hipStream_t>(stream));
@@ -392,12 +396,14 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
     d.done = nullptr;
     d.n_seq = j.n_seq;
     d.n_lit = j.n_lit;
+    d.spill = nullptr;
     ws_off += d.ws_len;
   }
   if (n_jobs && hipMemcpy(b->d_jobs, dj.data(), n_jobs * sizeof(gmpk::DevJob), hipMemcpyHostToDevice) != hipSuccess) {
     gmp_batch_destroy(b);
     return GMP_EDEVICE;
   }
+  b->h_jobs = std::move(dj);
   *out = b;
   return GMP_OK;
 }
@@ -405,7 +411,7 @@ extern "C" gmp_status gmp_batch_create(gmp_ctx* c, const gmp_job* h_jobs, uint32
 namespace {
 
 struct Launch {
-  uint32_t waves = 1, persistent = 0, workgroups = 0;
+  uint32_t waves = 1, persistent = 0, workgroups = 0, rounds = 0;
 };
 
 gmp_status launch_params(const gmp_batch* b, const gmp_tuning* tuning, Launch* l) {
@@ -414,17 +420,49 @@ gmp_status launch_params(const gmp_batch* b, const gmp_tuning* tuning, Launch* l
     x.waves = tuning->waves_per_block;
     x.persistent = tuning->persistent;
     x.workgroups = tuning->workgroups;
+    x.rounds = tuning->rounds_per_launch;
   }
   if (x.waves != 1 && x.waves != 2 && x.waves != 4 && x.waves != 7) return GMP_EINVAL;
-  if (x.persistent > 1) return GMP_EINVAL;
+  if (x.persistent > 1 || x.rounds > 64) return GMP_EINVAL;
   if (x.persistent && x.workgroups == 0) x.workgroups = (uint32_t)b->num_cu;
   *l = x;
   return GMP_OK;
 }
 
-gmp_status batch_launch(gmp_batch* b, uint32_t flags, const Launch& l, hipStream_t s) {
-  if (gmpk_launch(b->d_jobs, b->n, flags, l.waves, l.persistent, l.workgroups, b->d_queue, b->d_first_err, s) != 0)
+// The spill lists of multi-launch resolution: allocated once, on first use,
+// and named in the device job table from then on (a kernel only writes them
+// when its launch resolves a bounded number of rounds).
+gmp_status batch_spill_areas(gmp_batch* b) {
+  if (b->d_spill || b->n == 0) return GMP_OK;
+  uint64_t total = 0;
+  for (const gmpk::DevJob& j : b->h_jobs) total += (gmpk::spill_bytes(j.n_seq) + 255) / 256 * 256;
+  if (hipMalloc(&b->d_spill, total) != hipSuccess) {
+    b->d_spill = nullptr;
+    return GMP_ENOMEM;
+  }
+  uint64_t off = 0;
+  for (gmpk::DevJob& j : b->h_jobs) {
+    j.spill = b->d_spill + off;
+    off += (gmpk::spill_bytes(j.n_seq) + 255) / 256 * 256;
+  }
+  if (hipMemcpy(b->d_jobs, b->h_jobs.data(), b->n * sizeof(gmpk::DevJob), hipMemcpyHostToDevice) != hipSuccess)
     return GMP_EDEVICE;
+  return GMP_OK;
+}
+
+// One run of the batch: the decoding launch and, with a bounded number of
+// rounds per launch, the later launches that resolve the spill lists
+// (ceil(64 / R) - 1 of R rounds each, then one that finishes every list).
+gmp_status batch_launch(gmp_batch* b, uint32_t flags, const Launch& l, hipStream_t s) {
+  const uint32_t rounds = (flags & GMP_MODE_MASK) == GMP_MODE_DE || (flags & GMP_MODE_MASK) == GMP_MODE_SC
+                              ? 0u : l.rounds;
+  const uint32_t kflags = flags | (rounds << GMPK_ROUNDS_SHIFT);
+  if (gmpk_launch(b->d_jobs, b->n, kflags, l.waves, l.persistent, l.workgroups, b->d_queue, b->d_first_err, s) != 0)
+    return GMP_EDEVICE;
+  if (rounds == 0) return GMP_OK;
+  const uint32_t later = (64 + rounds - 1) / rounds - 1;
+  for (uint32_t k = 0; k <= later; k++)
+    if (gmpk_launch_spills(b->d_jobs, b->n, k < later ? rounds : 0u, k & 1u, nullptr, s) != 0) return GMP_EDEVICE;
   return GMP_OK;
 }
 
@@ -444,6 +482,7 @@ extern "C" gmp_status gmp_batch_run(gmp_ctx* c, gmp_batch* b, uint32_t flags, co
   if (st != GMP_OK) return st;
   if (b->n == 0) return GMP_OK;
   HIP_OK(hipSetDevice(b->device));
+  if (l.rounds && (st = batch_spill_areas(b)) != GMP_OK) return st;
   return batch_launch(b, flags, l, static_cast<hipStream_t>(stream));
 }
 
@@ -453,6 +492,7 @@ extern "C" gmp_status gmp_batch_graph_create(gmp_ctx* c, gmp_batch* b, uint32_t 
   gmp_status st = launch_params(b, tuning, &l);
   if (st != GMP_OK) return st;
   HIP_OK(hipSetDevice(b->device));
+  if (l.rounds && (st = batch_spill_areas(b)) != GMP_OK) return st;
   graph_release(b);
   if (!b->capture) HIP_OK(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
   HIP_OK(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
@@ -486,17 +526,30 @@ extern "C" gmp_status gmp_autotune(gmp_ctx* c, gmp_batch* b, uint32_t flags, uin
   const hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<Launch> cands;
   for (uint32_t w : {1u, 2u, 4u, 7u}) {
-    cands.push_back({w, 0u, 0u});
-    cands.push_back({w, 1u, (uint32_t)b->num_cu});
-    cands.push_back({w, 1u, 2u * (uint32_t)b->num_cu});
+    cands.push_back({w, 0u, 0u, 0u});
+    cands.push_back({w, 1u, (uint32_t)b->num_cu, 0u});
+    cands.push_back({w, 1u, 2u * (uint32_t)b->num_cu, 0u});
   }
+  // launch shapes first (every round in one launch), then rounds per launch
+  // on the winning shape
+  const size_t n_shapes = cands.size();
   std::vector<hipEvent_t> ev(reps + 1, nullptr);
   gmp_status st = GMP_OK;
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) st = GMP_EDEVICE;
   float best_t = -1.0f;
   Launch win = cands[0];
+  const bool mrr_possible = (flags & GMP_MODE_MASK) != GMP_MODE_DE && (flags & GMP_MODE_MASK) != GMP_MODE_SC;
   for (size_t k = 0; st == GMP_OK && k < cands.size(); k++) {
+    if (k + 1 == n_shapes && mrr_possible && batch_spill_areas(b) == GMP_OK) {
+      // after the last shape: rounds per launch on the winner so far
+      for (uint32_t r : {1u, 4u, 16u}) cands.push_back({0u, 0u, 0u, r});
+    }
+    if (k >= n_shapes) {
+      const uint32_t r = cands[k].rounds;
+      cands[k] = win;
+      cands[k].rounds = r;
+    }
     if (b->n && (st = batch_launch(b, flags, cands[k], s)) != GMP_OK) break;  // untimed warm-up
     if (hipEventRecord(ev[0], s) != hipSuccess) st = GMP_EDEVICE;
     for (uint32_t r = 0; st == GMP_OK && r < reps; r++) {
@@ -523,7 +576,7 @@ extern "C" gmp_status gmp_autotune(gmp_ctx* c, gmp_batch* b, uint32_t flags, uin
   best->waves_per_block = win.waves;
   best->persistent = win.persistent;
   best->workgroups = win.workgroups;
-  best->reserved = 0;
+  best->rounds_per_launch = win.rounds;
   if (best_ms) *best_ms = best_t;
   return GMP_OK;
 }
@@ -534,6 +587,7 @@ extern "C" void gmp_batch_destroy(gmp_batch* b) {
   graph_release(b);
   if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_spill) (void)hipFree(b->d_spill);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_queue) (void)hipFree(b->d_queue);
   delete b;

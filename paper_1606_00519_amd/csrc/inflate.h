@@ -10,6 +10,12 @@
 #define GMPK_MODE_MASK 3u
 #define GMPK_FLAG_STATS 0x100u
 #define GMPK_FLAG_VERIFY_DE 0x200u
+// Multi-round resolution over several launches: the first launch resolves at
+// most R rounds per group of 64 sequences (R in bits 16-23 of the kernel's
+// flags; 0 = every round), writing the back-references still pending to the
+// block's spill list; later launches resolve the list (gmpk_launch_spills).
+#define GMPK_ROUNDS_SHIFT 16u
+#define GMPK_ROUNDS_MASK 0xFF0000u
 
 namespace gmpk {
 
@@ -29,8 +35,14 @@ struct DevJob {
   uint32_t* stats;      // optional kStatsWords counters (see below)
   uint32_t* done;       // optional counter in host-visible memory: +1 when the block has finished
   uint32_t n_seq, n_lit;
+  uint8_t* spill;       // optional spill area (spill_bytes(n_seq)): back-references left for later launches
 };
-static_assert(sizeof(DevJob) == 96, "DevJob layout");
+static_assert(sizeof(DevJob) == 104, "DevJob layout");
+
+// A block's spill area: two u32 counts (lists A and B), padding to 16 bytes,
+// then lists A and B of up to n_seq entries each {u32 destination, u32
+// distance << 9 | length}, in destination order.
+__host__ __device__ inline uint64_t spill_bytes(uint32_t n_seq) { return 16 + 16ull * n_seq; }
 
 // Per-block counters written with GMPK_FLAG_STATS when DevJob::stats is set:
 //   [0] how the sub-blocks were decoded: 1 segmented, 2 one lane per sub-block
@@ -40,6 +52,7 @@ static_assert(sizeof(DevJob) == 96, "DevJob layout");
 //   [5] the wait that ran out first when the status is ESTALL (0: none)
 //   [6] why segmented decoding was not accepted (reason bits, 0: accepted)
 //   [7] 1 when segmented decoding was attempted a second time
+//   [8] back-references the first launch left to later launches (rounds per launch)
 //   [16 + r] back-reference bytes copied in round r + 1 (r < 64), all groups
 constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 
@@ -92,6 +105,12 @@ extern "C" int gmpk_launch(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t
 // *word = 0; and *out = *word, *word = 0 in one atomic exchange.
 extern "C" int gmpk_clear_word(int32_t* word, hipStream_t stream);
 extern "C" int gmpk_take_word(int32_t* word, int32_t* out, hipStream_t stream);
+// Later launches of multi-launch resolution: every job's spill list `parity`
+// (0: A, 1: B) is resolved, at most `rounds` rounds per group of 64 entries (0 =
+// all), what is still pending going to the other list.  d_remaining (may be
+// null) receives the number of entries left.
+extern "C" int gmpk_launch_spills(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t rounds, uint32_t parity,
+                                  uint32_t* d_remaining, hipStream_t stream);
 // One block, seven decoder wavefronts, the job descriptor passed by value in
 // the kernel arguments (no device job table).
 extern "C" int gmpk_launch_single(const gmpk::DevJob* h_job, uint32_t flags, int32_t* d_first_err,

@@ -226,6 +226,7 @@ struct Misc {
   // groups resolved in pieces, DE groups resolved by rounds
   uint32_t rbytes[64];
   uint32_t n_split, n_de_rounds, a2_path, n_repaired, stall_site, seg_reject, seg_retry;
+  uint32_t spill_n;  // back-references written to the block's spill list (groups append in order)
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
@@ -239,9 +240,16 @@ constexpr uint32_t kSegFail = 1, kSegPass = 2, kSegMaybe = 4, kSegMid = 8, kSegR
 constexpr uint32_t kRejIndex = 1, kRejCode = 2, kRejOver = 4, kRejMeet = 8, kRejLast = 16, kRejRun = 32,
                    kRejCount = 64, kRejRepair = 128;
 struct Seg {
-  uint32_t sub_start[kSubMax + 1];  // first payload bit of each sub-block; [n_sub] = payload bits
-  uint32_t sub_end[kSubMax];        // bit after each sub-block's end symbol
-  uint32_t cnt_seq[kSubMax], cnt_lit[kSubMax], cnt_raw[kSubMax];  // tokens decoded per sub-block, all lanes
+  union {
+    struct {
+      uint32_t sub_start[kSubMax + 1];  // first payload bit of each sub-block; [n_sub] = payload bits
+      uint32_t sub_end[kSubMax];        // bit after each sub-block's end symbol
+      uint32_t cnt_seq[kSubMax], cnt_lit[kSubMax], cnt_raw[kSubMax];  // tokens decoded per sub-block, all lanes
+    };
+    // resolution over several launches (A3-A6 only): one bit per output
+    // window position, set while the byte there waits for a later launch
+    uint32_t pend[kRing / 32];
+  };
   uint32_t entry[kMaxLanes], exit_at[kMaxLanes];  // first / past-last symbol boundary each lane decoded
   uint32_t nrec[kMaxLanes], nlit[kMaxLanes];      // records / literal bytes each lane wrote
   uint32_t tail[kMaxLanes];                       // literals after a lane's last record, run still open
@@ -1259,6 +1267,11 @@ struct LzArgs {
   GMEM uint8_t* out;
   uint32_t n_seq, n_lit, raw_len;
   uint32_t res;      // kResMRR, kResDE (one pass) or kResSC (one back-reference at a time)
+  // Multi-round resolution over several launches (kResMRR with a spill area):
+  // at most max_rounds rounds per group here, the back-references still
+  // pending, and those that read their bytes, go to the spill list
+  uint32_t max_rounds;
+  GMEM uint32_t* spill;  // list A: {destination, distance << 9 | length} entries (null: no spilling)
   bool verify_de;    // a DE group that breaks the DE rule is an error (it is resolved by rounds either way)
   bool stats;        // count bytes per round, split groups and DE groups resolved by rounds
   GMEM uint8_t* rounds;
@@ -1472,6 +1485,50 @@ __device__ __forceinline__ bool wait_done(uint32_t pos) {
   return wait_at_least(&s_misc.done_upto, pos, seen, kSiteDone);
 }
 
+// Pending-byte bitmap of multi-launch resolution (window positions, like the
+// output window).  A group clears its own positions before it writes them; a
+// back-reference left pending marks its destination; a back-reference whose
+// source holds a marked byte cannot be copied in this launch either.
+__device__ __forceinline__ uint32_t pend_mask(uint32_t p, uint32_t hi, uint32_t& n) {
+  const uint32_t b = p & 31;
+  n = min(32u - b, hi - p);
+  return (n == 32 ? ~0u : ((1u << n) - 1u)) << b;
+}
+__device__ bool pend_any(uint32_t lo, uint32_t hi) {
+  for (uint32_t p = lo, n; p < hi; p += n) {
+    const uint32_t m = pend_mask(p, hi, n);
+    if (s_seg.pend[(p >> 5) & (kRing / 32 - 1)] & m) return true;
+  }
+  return false;
+}
+__device__ void pend_mark(uint32_t lo, uint32_t hi) {
+  for (uint32_t p = lo, n; p < hi; p += n) atomicOr(&s_seg.pend[(p >> 5) & (kRing / 32 - 1)], pend_mask(p, hi, n));
+}
+// the whole wavefront clears positions [lo, hi)
+__device__ void pend_clear(uint32_t lo, uint32_t hi, uint32_t lane) {
+  if (hi <= lo) return;
+  for (uint32_t w = (lo >> 5) + lane; w <= ((hi - 1) >> 5); w += 64) {
+    const uint32_t p = max(lo, 32 * w), e = min(hi, 32 * w + 32);
+    uint32_t n;
+    atomicAnd(&s_seg.pend[w & (kRing / 32 - 1)], ~pend_mask(p, e, n));
+  }
+}
+// Append this group's (or piece's) pending back-references to the spill
+// list, in sequence order: called once every earlier group is final, so the
+// list stays in destination order.
+__device__ void spill_append(const LzArgs& a, bool spilled, uint32_t dst, uint32_t D, uint32_t M, uint32_t lane) {
+  const uint64_t sv = __ballot(spilled);
+  if (!sv) return;
+  const uint32_t base = s_misc.spill_n;
+  if (spilled) {
+    const uint32_t i = base + (uint32_t)__popcll(sv & ((1ull << lane) - 1ull));
+    a.spill[2 * i] = dst;
+    a.spill[2 * i + 1] = (D << 9) | M;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) s_misc.spill_n = base + (uint32_t)__popcll(sv);
+}
+
 // Resolver wavefront w of kRes.
 template <int kRes>
 __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
@@ -1542,8 +1599,10 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
                    (M0 == 0 || (D >= M0 && (src0 & kRingMask) + ((M0 + 15) & ~15u) <= kRing)) &&
                    (L == 0 || (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing));
     const bool plain = !__ballot(!lane_plain);
+    const bool spill_mode = a.spill && a.res == kResMRR;
     if (fast) {
       if (!wait_window(g_end)) break;
+      if (spill_mode) pend_clear(g_out, g_end, lane);
       // A4: literal strings into the window, ahead of earlier groups; long
       // runs are spread over the whole wavefront
       const uint32_t max_l = readlane(wave_incl_max(valid ? L : 0u), 63);
@@ -1593,7 +1652,24 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // before the groups in front of it have finished.
       const uint32_t need = min(readlane(wave_incl_max(has ? need_end : 0u), 63), g_out);
       if (!wait_done(need)) break;
-      if (plain) {
+      bool spilled = false;
+      if (spill_mode) {
+        // rounds past max_rounds, and copies whose source holds a byte that
+        // waits for a later launch, are left to the spill list
+        for (uint32_t r = 1; r <= rounds; r++) {
+          if (my_round == r) {
+            if ((a.max_rounds && r > a.max_rounds) || pend_any(src0, need_end)) {
+              pend_mark(dst, dst + M);
+              spilled = true;
+            } else if (lane_plain) {
+              copy_nowrap(ring, dst, src0, M);
+            } else {
+              copy_match(ring, dst, M, D);
+            }
+          }
+        }
+        if (a.max_rounds) rounds = min(rounds, a.max_rounds);
+      } else if (plain) {
         for (uint32_t r = 1; r <= rounds; r++) {
           if (my_round == r) copy_nowrap(ring, dst, src0, M);
         }
@@ -1609,10 +1685,11 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       }
       // its output is final once everything in front of it is
       if (!wait_done(g_out)) break;
+      if (spill_mode) spill_append(a, spilled, dst, D, M, lane);
       lds_release(&s_misc.done_upto, g_end);
       if (a.stats) {
         for (uint32_t r = 1; r <= rounds && r <= 64; r++) {
-          const uint32_t b = readlane(wave_incl_scan(my_round == r ? M : 0u), 63);
+          const uint32_t b = readlane(wave_incl_scan(my_round == r && !spilled ? M : 0u), 63);
           if (lane == 0) atomicAdd(&s_misc.rbytes[r - 1], b);
         }
       }
@@ -1633,6 +1710,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
               ok = false;
               break;
             }
+            if (spill_mode) pend_clear(base, base + P, lane);
             stream_lits_hbm(lits + slo, base, P, lane);
             lds_release(&s_misc.done_upto, base + P);
             base += P;
@@ -1663,6 +1741,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
           ok = false;
           break;
         }
+        if (spill_mode) pend_clear(base, piece_end, lane);
         // A4: literal strings into the window
         if (active && L) {
           if (lits_staged) {
@@ -1694,13 +1773,28 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
         } else {
           // A5: Multi-Round Resolution
           const uint32_t need_end = dst - D + min(M, D);
+          bool spilled = false;
           for (;;) {
             const uint64_t votes = __ballot(pending);
             if (votes == 0) break;
+            if (spill_mode && a.max_rounds && rounds >= a.max_rounds) {
+              // the rest of the group's back-references wait for a later launch
+              if (pending) {
+                pend_mark(dst, dst + M);
+                spilled = true;
+                pending = false;
+              }
+              break;
+            }
             const uint32_t hwm = readlane(dst, (uint32_t)__builtin_ctzll(votes));
             const bool can = pending && need_end <= hwm;
             if (can) {
-              copy_match(ring, dst, M, D);
+              if (spill_mode && pend_any(dst - D, need_end)) {
+                pend_mark(dst, dst + M);
+                spilled = true;
+              } else {
+                copy_match(ring, dst, M, D);
+              }
               pending = false;
             }
             if (a.stats) {
@@ -1709,6 +1803,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
             }
             rounds++;
           }
+          if (spill_mode) spill_append(a, spilled, dst, D, M, lane);
         }
         lds_release(&s_misc.done_upto, piece_end);
         released = piece_end;
@@ -2012,6 +2107,8 @@ __device__ void resolve_phase(const LzArgs& a) {
     resolve_groups<kRes>(a, wave);
   }
   __syncthreads();
+  // the spill list's length (none after an error: the block has failed)
+  if (a.spill && t == 0) a.spill[-4] = (sh.err || sh.abort) ? 0u : sh.spill_n;
 }
 
 // ---------------------------------------------------------------- Gompresso/Byte
@@ -2120,6 +2217,8 @@ __device__ int inflate_byte_block(const DevJob& job, uint32_t flags) {
   a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
   a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
+  a.max_rounds = (flags & GMPK_ROUNDS_MASK) >> GMPK_ROUNDS_SHIFT;
+  a.spill = a.max_rounds && job.spill ? (GMEM uint32_t*)(gmem(job.spill) + 16) : nullptr;
   a.priv = nullptr;
   if (n_seq) resolve_phase<kDec>(a);
   stamp(job, 3);
@@ -2145,6 +2244,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     sh.stall_site = 0;
     sh.seg_reject = 0;
     sh.seg_retry = 0;
+    sh.spill_n = 0;
   }
   if (t < 64) sh.rbytes[t] = 0;
   __syncthreads();
@@ -2294,6 +2394,8 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
   a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
+  a.max_rounds = (flags & GMPK_ROUNDS_MASK) >> GMPK_ROUNDS_SHIFT;
+  a.spill = a.max_rounds && job.spill ? (GMEM uint32_t*)(gmem(job.spill) + 16) : nullptr;
   a.priv = nullptr;
   if (segmented) {
     const uint64_t cap_rec = lane_cap_rec(n_seq, kLanes), cap_lit = lane_cap_lit(n_lit, job.comp_len, kLanes);
@@ -2310,6 +2412,8 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
 // word, its statistics and its completion counter.
 template <int kDec, int kMode>
 __device__ void run_block(const DevJob& job, uint32_t flags, int32_t* first_err) {
+  // an empty spill list unless resolution leaves back-references to later launches
+  if (job.spill && threadIdx.x < 2) gmem((uint32_t*)job.spill)[threadIdx.x] = 0;
   const int st = inflate_block<kDec, kMode>(job, flags);
   const uint32_t t = threadIdx.x;
   __syncthreads();
@@ -2329,6 +2433,7 @@ __device__ void run_block(const DevJob& job, uint32_t flags, int32_t* first_err)
       o[5] = s_misc.stall_site;
       o[6] = s_misc.seg_reject;
       o[7] = s_misc.seg_retry;
+      o[8] = s_misc.spill_n;
     }
   }
   if (job.done) {
@@ -2376,6 +2481,72 @@ __global__ __launch_bounds__(block_threads<kDec>()) void inflate_persistent_kern
     if (!(flags & GMPK_FLAG_STATS)) job.times = nullptr;
     run_block<kDec, kMode>(job, flags, first_err);
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- later launches
+// Multi-Round Resolution over several launches (the paper's variant in which
+// the back-references still unresolved after a round are written to device
+// memory and a later kernel resolves them, section "Performance Impact of
+// Nested back-references").  One wavefront per block walks the block's spill
+// list, 64 entries at a time, straight in the output in HBM: everything
+// outside the destinations still pending is final there.  An entry is copied
+// once its source ends at or below the lowest destination still pending (the
+// entries are in destination order; with the lowest entry re-spilled in this
+// launch that mark covers every pending byte).  At most `rounds` rounds per 64
+// entries (0: until none is pending); the rest go to the other list, in order.
+// A copy of length n at distance d repeats the d bytes before its destination
+// (byte-forward semantics), so it only reads bytes that were final before it.
+__global__ __launch_bounds__(64) void resolve_spills_kernel(const DevJob* __restrict__ jobs, uint32_t n_jobs,
+                                                            uint32_t rounds, uint32_t parity,
+                                                            uint32_t* d_remaining) {
+  if (blockIdx.x >= n_jobs) return;
+  const DevJob job = jobs[blockIdx.x];
+  if (!job.spill) return;
+  const uint32_t lane = lane_id();
+  GMEM uint32_t* head = gmem((uint32_t*)job.spill);
+  GMEM uint32_t* in = head + 4 + 2ull * job.n_seq * parity;
+  GMEM uint32_t* out_list = head + 4 + 2ull * job.n_seq * (parity ^ 1u);
+  const uint32_t n_in = min(head[parity], job.n_seq);
+  uint8_t* out = job.out;
+  uint32_t n_out = 0, low_pending = kDone;
+  for (uint32_t b = 0; b < n_in; b += 64) {
+    const uint32_t i = b + lane;
+    const bool valid = i < n_in;
+    const uint32_t dst = valid ? in[2 * i] : 0u, dl = valid ? in[2 * i + 1] : 0u;
+    const uint32_t D = dl >> 9, M = dl & 511u;
+    // entries that do not fit the block's output are dropped (a failed block's list)
+    const bool ok = valid && M && D && D <= dst && (uint64_t)dst + M <= job.out_len;
+    const uint32_t need_end = dst - D + min(M, D);
+    bool pending = ok;
+    for (uint32_t r = 0;; r++) {
+      const uint64_t votes = __ballot(pending);
+      if (!votes || (rounds && r == rounds)) break;
+      const uint32_t hwm = min(readlane(dst, (uint32_t)__builtin_ctzll(votes)), low_pending);
+      const bool can = pending && need_end <= hwm;
+      if (can) {
+        const uint32_t src = dst - D, per = min(D, M);
+        for (uint32_t k = 0; k < M; k++) out[dst + k] = __hip_atomic_load(out + src + (k % per), __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT);
+      }
+      pending = pending && !can;
+      // this round's bytes are visible to the next round's loads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    const uint64_t left = __ballot(pending);
+    if (pending) {
+      const uint32_t o = n_out + (uint32_t)__popcll(left & ((1ull << lane) - 1ull));
+      out_list[2 * o] = dst;
+      out_list[2 * o + 1] = dl;
+    }
+    if (left) low_pending = min(low_pending, readlane(dst, (uint32_t)__builtin_ctzll(left)));
+    n_out += (uint32_t)__popcll(left);
+  }
+  if (lane == 0) {
+    head[parity ^ 1u] = n_out;
+    head[parity] = 0;
+    if (n_out && d_remaining) atomicAdd(d_remaining, n_out);
   }
 }
 
@@ -2453,6 +2624,14 @@ extern "C" int gmpk_launch_single(const gmpk::DevJob* h_job, uint32_t flags, int
       hipLaunchKernelGGL((inflate_single_kernel<7, GMPK_MODE_SC>), grid, block, 0, stream, job, flags, d_first_err);
       break;
   }
+  return hipGetLastError() == hipSuccess ? 0 : -8;
+}
+
+extern "C" int gmpk_launch_spills(const gmpk::DevJob* d_jobs, uint32_t n_jobs, uint32_t rounds, uint32_t parity,
+                                  uint32_t* d_remaining, hipStream_t stream) {
+  if (n_jobs == 0) return 0;
+  hipLaunchKernelGGL(gmpk::resolve_spills_kernel, dim3(n_jobs), dim3(64), 0, stream, d_jobs, n_jobs, rounds,
+                     parity & 1u, d_remaining);
   return hipGetLastError() == hipSuccess ? 0 : -8;
 }
 
