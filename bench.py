@@ -198,8 +198,8 @@ class StreamRun:
         self.sbatch = ctx.batch_create(sjobs, self.status)
         self.blocks, self.comp, self.raw = nb, len(s), raw
 
-    def run(self, flags: int, waves: int) -> None:
-        self.batch.run(flags, waves=waves, persistent=False)
+    def run(self, flags: int, waves: int, rounds_per_launch: int = 0) -> None:
+        self.batch.run(flags, waves=waves, persistent=False, rounds_per_launch=rounds_per_launch)
 
     def check(self, data: bytes, what: str) -> None:
         st = self.status.cpu().numpy()
@@ -376,6 +376,44 @@ def side_leg(ctx, name: str, data: bytes, streams: dict, steps: int, warmup: int
     return res
 
 
+def multilaunch_leg(ctx, data: bytes, stream: bytes, steps: int, warmup: int, waves: int) -> dict:
+    """Multi-Round Resolution over several launches on the headline MRR
+    stream: at most R rounds per group in the decoding launch, the pending
+    back-references resolved by later launches (the paper's alternative MRR
+    variant, section "Performance Impact of Nested back-references"), against
+    every round in one launch."""
+    import torch
+
+    import paper_1606_00519_amd as gmp
+    r = StreamRun(ctx, stream, len(data))
+    stream_h = torch.cuda.current_stream()
+    res = {}
+    for R in (0, 16, 4, 1):
+        for _ in range(warmup):
+            r.run(gmp.MODE_MRR, waves, R)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream_h)
+            r.run(gmp.MODE_MRR, waves, R)
+            b.record(stream_h)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        r.check(data, f"multi-launch R={R}")
+        # back-references the decoding launch left to later launches
+        r.sbatch.run(gmp.MODE_MRR | gmp.FLAG_STATS, waves=waves, persistent=False, rounds_per_launch=R)
+        torch.cuda.synchronize()
+        spilled = int(r.stats.cpu().numpy()[:r.blocks, gmp.STAT_SPILLED].astype(np.int64).sum())
+        r.check(data, f"multi-launch R={R} (stats run)")
+        launches = 1 if R == 0 else 1 + (64 + R - 1) // R
+        res[f"R{R}" if R else "all_rounds"] = {"rounds_per_launch": R, "launches": launches, "ms": round(ms, 4),
+                                               "GBps": round(len(data) / (ms / 1e3) / 1e9, 3),
+                                               "spilled_backrefs": spilled}
+        log(f"multi-launch R={R}: {res[f'R{R}' if R else 'all_rounds']}")
+    r.close()
+    return res
+
+
 def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict:
     """Speed against back-reference nesting depth (section "Performance Impact
     of Nested back-references"): byte-level blocks of 1 MiB whose token
@@ -499,7 +537,7 @@ def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads
     del blocks
     tun, tms = db.batch.autotune(gmp.MODE_AUTO, reps=3)
     db.batch.graph_create(gmp.MODE_AUTO, waves=tun["waves"], persistent=tun["persistent"],
-                          workgroups=tun["workgroups"])
+                          workgroups=tun["workgroups"], rounds_per_launch=tun["rounds_per_launch"])
     stream = torch.cuda.current_stream()
 
     def timed(run):
@@ -528,7 +566,8 @@ def batched_leg(ctx, text: bytes, n_items: int, steps: int, warmup: int, threads
     # the same launch shape without the graph and the device queue: one
     # workgroup per job at the tuned wavefront count, then at one wavefront
     db.out.zero_()
-    same_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=tun["waves"], persistent=False))
+    same_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=tun["waves"], persistent=False,
+                                         rounds_per_launch=tun["rounds_per_launch"]))
     check("plain, tuned waves")
     db.out.zero_()
     plain_ms = timed(lambda: db.batch.run(gmp.MODE_AUTO, waves=1, persistent=False))
@@ -679,7 +718,7 @@ def main() -> int:
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
                     help="decoder wavefronts per block (phase A); with 7, four of them resolve in phase B")
-    ap.add_argument("--legs", default="byte,csv,nesting,batched,serve",
+    ap.add_argument("--legs", default="byte,csv,nesting,multilaunch,batched,serve",
                     help="side legs beside the headline (comma-separated; '' = headline only)")
     ap.add_argument("--csv-mib", type=int, default=1024, help="size of the low-entropy CSV configuration")
     ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items")
@@ -732,6 +771,9 @@ def main() -> int:
         del csv, cs
     if "nesting" in legs:
         side["nesting"] = nesting_leg(ctx, args.steps, args.warmup, args.waves)
+    if "multilaunch" in legs:
+        side["multilaunch"] = multilaunch_leg(ctx, data, streams["mrr"], max(5, args.steps // 2), args.warmup,
+                                              args.waves)
     batched = serving = None
     if "batched" in legs and args.batch_items > 0:
         batched = batched_leg(ctx, data, args.batch_items, min(args.steps, 5), 1, args.threads)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import CANARY, GUARD, decode_batch
+from gpu_util import CANARY, GUARD
 
 pytestmark = pytest.mark.gpu
 
