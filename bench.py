@@ -414,6 +414,63 @@ def multilaunch_leg(ctx, data: bytes, stream: bytes, steps: int, warmup: int, wa
     return res
 
 
+def compress_leg(ctx, data: bytes, cpu_sizes: dict, steps: int, warmup: int, waves: int) -> dict:
+    """GPU compression of the headline text into byte-level blocks of 1 MiB
+    (section "Parallel Compression"), ordinary and with Dependency
+    Elimination: compressed GB/s (input bytes per second), ratio against the
+    CPU compressor's, and the round trip through the GPU decoder; a sample of
+    blocks also passes the CPU reference's format check."""
+    import torch
+
+    import oracle
+    import paper_1606_00519_amd as gmp
+    n = len(data)
+    bs = 1 << 20
+    nb = (n + bs - 1) // bs
+    d_in = torch.frombuffer(bytearray(data), dtype=torch.uint8).cuda()
+    cap = (gmp.compress_bound(bs) + 255) & ~255
+    outs = torch.zeros(nb * cap, dtype=torch.uint8, device="cuda")
+    lens = torch.zeros(nb, dtype=torch.int64, device="cuda")
+    status = torch.full((nb,), 99, dtype=torch.int32, device="cuda")
+    jobs = [gmp.CompressJob(d_in.data_ptr() + b * bs, min(bs, n - b * bs), outs.data_ptr() + b * cap, cap,
+                            lens.data_ptr() + 8 * b, status.data_ptr() + 4 * b) for b in range(nb)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for de in (0, 1):
+        for _ in range(warmup):
+            ctx.compress_batch(jobs, de=de)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream)
+            ctx.compress_batch(jobs, de=de)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        if not np.all(status.cpu().numpy() == 0):
+            raise RuntimeError("compress: a block failed")
+        ln = lens.cpu().numpy().astype(np.int64)
+        o = outs.cpu().numpy()
+        blocks = [o[b * cap:b * cap + int(ln[b])].tobytes() for b in range(nb)]
+        for b in (0, nb // 2, nb - 1):
+            raw = data[b * bs:(b + 1) * bs]
+            if oracle.validate_block(blocks[b]) != 0 or oracle.decompress_block(blocks[b]) != (0, raw):
+                raise RuntimeError(f"compress: block {b} fails the CPU reference's check")
+        s = oracle.assemble_stream(blocks, bs, n)
+        r = StreamRun(ctx, s, n)
+        r.run(gmp.MODE_AUTO, waves)
+        torch.cuda.synchronize()
+        r.check(data, f"compress de={de} round trip")
+        r.close()
+        comp = len(s)
+        res["de" if de else "ordinary"] = {
+            "ms": round(ms, 4), "GBps": round(n / (ms / 1e3) / 1e9, 3), "ratio": round(n / comp, 4),
+            "cpu_compressor_ratio": round(n / cpu_sizes[de], 4),
+            "hbm_GBps": round((n + comp) / (ms / 1e3) / 1e9, 2)}
+        log(f"compress de={de}: {res['de' if de else 'ordinary']}")
+    return res
+
+
 def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict:
     """Speed against back-reference nesting depth (section "Performance Impact
     of Nested back-references"): byte-level blocks of 1 MiB whose token
@@ -718,7 +775,7 @@ def main() -> int:
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
                     help="decoder wavefronts per block (phase A); with 7, four of them resolve in phase B")
-    ap.add_argument("--legs", default="byte,csv,nesting,multilaunch,batched,serve",
+    ap.add_argument("--legs", default="byte,compress,csv,nesting,multilaunch,batched,serve",
                     help="side legs beside the headline (comma-separated; '' = headline only)")
     ap.add_argument("--csv-mib", type=int, default=1024, help="size of the low-entropy CSV configuration")
     ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items")
@@ -755,6 +812,9 @@ def main() -> int:
         side["byte"] = side_leg(ctx, "byte", data, {"mrr": (bs[0], gmp.MODE_MRR), "de": (bs[1], gmp.MODE_DE),
                                                     "sc": (bs[0], gmp.MODE_SC)},
                                 args.steps, args.warmup, args.waves, copy_ref["GBps"])
+        if "compress" in legs:
+            side["compress"] = compress_leg(ctx, data, {0: len(bs[0]), 1: len(bs[1])}, max(3, args.steps // 4),
+                                            1, args.waves)
         del bs
     if "csv" in legs:
         t0 = time.time()

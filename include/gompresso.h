@@ -293,6 +293,43 @@ gmp_status gmp_batch_graph_launch(gmp_ctx* ctx, gmp_batch* batch, void* stream);
 gmp_status gmp_autotune(gmp_ctx* ctx, gmp_batch* batch, uint32_t flags, uint32_t reps, gmp_tuning* best,
                         float* best_ms, void* stream);
 
+/* ---- compression on the GPU (Gompresso/Byte) ------------------------------------ */
+/* Compress independent data blocks into byte-level blocks (the format above),
+ * one workgroup per block (section "Parallel Compression": each block is
+ * compressed by a group of threads that find matches in parallel; the byte
+ * level encoding needs no Huffman stage).  With de = 1 every group of 64
+ * sequences obeys the Dependency Elimination rule (section "Dependency
+ * Elimination (DE)"): each of its back-references ends at or before the
+ * destination of the group's first one, so the decoder resolves the group in
+ * one pass.  Matches come from hash chains of 3-byte keys (the most recent
+ * positions first, a bounded number of them) and from distances 1-4; the
+ * parse is greedy.  Several compressed forms of a block are valid: the output
+ * is checked by decoding, not against another compressor's bytes. */
+typedef struct {
+  uint32_t window;     /* longest distance, 1..32768 */
+  uint32_t max_match;  /* 3..258 */
+  uint32_t de;         /* 0: ordinary LZ77 stream, 1: Dependency Elimination (group of 64) */
+  uint32_t reserved;
+} gmp_compress_params;
+typedef struct {
+  const uint8_t* d_in;  /* device: the block's bytes */
+  uint64_t in_len;      /* at most GMP_COMPRESS_MAX_BLOCK */
+  uint8_t* d_out;       /* device, 16-byte aligned: the compressed block */
+  uint64_t out_cap;     /* at least gmp_compress_bound(in_len) */
+  uint64_t* d_out_len;  /* device: receives the compressed block's size */
+  int32_t* d_status;    /* device: GMP_OK, or GMP_ESTALL if a bounded wait ran out */
+} gmp_compress_job;
+#define GMP_COMPRESS_MAX_BLOCK (64u << 20)
+/* Largest compressed size of a block of in_len bytes. */
+uint64_t gmp_compress_bound(uint64_t in_len);
+/* Compress n_jobs blocks, asynchronously on `stream`.  The context holds the job
+ * table and a workspace of 8 bytes per input byte (grown on demand; the call
+ * waits for the context's previous single call first).  EINVAL on bad
+ * parameters, a misaligned output, a capacity below the bound or a block over
+ * GMP_COMPRESS_MAX_BLOCK. */
+gmp_status gmp_compress_batch(gmp_ctx* ctx, const gmp_compress_job* h_jobs, uint32_t n_jobs,
+                              const gmp_compress_params* params, void* stream);
+
 /* ---- request loop (continuous batching on one GPU) ------------------------------ */
 /* A server admits decompression requests of mixed sizes as they arrive and runs
  * them concurrently.  A scheduler thread admits requests first come first served

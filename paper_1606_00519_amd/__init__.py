@@ -38,7 +38,8 @@ EXPORTS = ("gmp_ctx_create", "gmp_ctx_destroy", "gmp_strerror", "gmp_poll", "gmp
            "gmp_decompress_block", "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run",
            "gmp_batch_destroy", "gmp_batch_graph_create", "gmp_batch_graph_launch", "gmp_autotune",
            "gmp_server_create", "gmp_server_submit", "gmp_server_poll", "gmp_server_drain", "gmp_server_stats",
-           "gmp_server_destroy", "gmp_workspace_bytes", "gmp_noalloc_init", "gmp_decompress_block_noalloc")
+           "gmp_server_destroy", "gmp_workspace_bytes", "gmp_noalloc_init", "gmp_decompress_block_noalloc",
+           "gmp_compress_bound", "gmp_compress_batch")
 
 
 class GmpError(RuntimeError):
@@ -58,6 +59,15 @@ class Job(C.Structure):
     _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("d_out", C.c_void_p), ("out_len", C.c_uint64),
                 ("n_seq", C.c_uint32), ("n_lit", C.c_uint32), ("d_rounds", C.c_void_p), ("d_times", C.c_void_p),
                 ("d_stats", C.c_void_p), ("format", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class CompressParams(C.Structure):
+    _fields_ = [("window", C.c_uint32), ("max_match", C.c_uint32), ("de", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class CompressJob(C.Structure):
+    _fields_ = [("d_in", C.c_void_p), ("in_len", C.c_uint64), ("d_out", C.c_void_p), ("out_cap", C.c_uint64),
+                ("d_out_len", C.c_void_p), ("d_status", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -115,11 +125,15 @@ def _load():
     L.gmp_server_destroy.argtypes = [vp]
     L.gmp_server_destroy.restype = None
     L.gmp_noalloc_init.argtypes = []
+    L.gmp_compress_bound.argtypes = [C.c_uint64]
+    L.gmp_compress_bound.restype = C.c_uint64
+    L.gmp_compress_batch.argtypes = [vp, C.POINTER(CompressJob), u32, C.POINTER(CompressParams), vp]
     L.gmp_decompress_block_noalloc.argtypes = [vp, sz, vp, sz, vp, sz, vp, u32, vp]
     for fn in ("gmp_ctx_create", "gmp_poll", "gmp_block_info_parse", "gmp_stream_info", "gmp_decompress_block",
                "gmp_decompress_stream", "gmp_batch_create", "gmp_batch_run", "gmp_batch_graph_create",
                "gmp_batch_graph_launch", "gmp_autotune", "gmp_server_create", "gmp_server_submit",
-               "gmp_server_drain", "gmp_server_stats", "gmp_noalloc_init", "gmp_decompress_block_noalloc"):
+               "gmp_server_drain", "gmp_server_stats", "gmp_noalloc_init", "gmp_decompress_block_noalloc",
+               "gmp_compress_batch"):
         getattr(L, fn).restype = i32
     return L
 
@@ -154,6 +168,11 @@ def block_info(h_block) -> dict:
     if st:
         raise GmpError(st, "gmp_block_info_parse")
     return {f: getattr(info, f) for f, _ in BlockInfo._fields_ if f != "reserved"}
+
+
+def compress_bound(in_len: int) -> int:
+    """Largest compressed size of a block (gmp_compress_bound)."""
+    return int(lib.gmp_compress_bound(in_len))
 
 
 def workspace_bytes(n_seq: int, n_lit: int, comp_len: int) -> int:
@@ -329,6 +348,15 @@ class Context:
                                        flags, _stream_handle(stream))
         if st:
             raise GmpError(st, "gmp_decompress_stream")
+
+    def compress_batch(self, jobs: list[CompressJob], window: int = 32768, max_match: int = 258, de: int = 0,
+                       stream=None) -> None:
+        """Compress blocks into byte-level blocks on the GPU (gmp_compress_batch, async)."""
+        arr = (CompressJob * max(len(jobs), 1))(*jobs)
+        prm = CompressParams(window, max_match, de, 0)
+        st = lib.gmp_compress_batch(self.handle, arr, len(jobs), C.byref(prm), _stream_handle(stream))
+        if st:
+            raise GmpError(st, "gmp_compress_batch")
 
     def batch_create(self, jobs: list[Job], status) -> Batch:
         return Batch(self, jobs, status)

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgompresso_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("inflate.hip", "noalloc.hip", "api.cpp", "server.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("inflate.hip", "compress.hip", "noalloc.hip", "api.cpp",
+                                                    "server.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

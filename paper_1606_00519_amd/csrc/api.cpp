@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/gompresso.h"
+#include "compress.h"
 #include "host_internal.h"
 #include "inflate.h"
 
@@ -59,6 +60,11 @@ struct gmp_ctx {
   int32_t* h_poll = nullptr;       // pinned
   hipEvent_t done = nullptr;       // recorded after the last single-call launch
   bool pending = false;
+  gmpc::CompressJob* d_cjobs = nullptr;  // job table of the compressor
+  gmpc::CompressJob* h_cjobs = nullptr;  // pinned staging for it
+  size_t cjobs_cap = 0;
+  uint8_t* d_cws = nullptr;              // the compressor's workspace
+  size_t cws_cap = 0;
 };
 
 struct gmp_batch {
@@ -198,6 +204,9 @@ extern "C" void gmp_ctx_destroy(gmp_ctx* c) {
   if (c->d_jobs) (void)hipFree(c->d_jobs);
   if (c->h_jobs) (void)hipHostFree(c->h_jobs);
   if (c->d_ws) (void)hipFree(c->d_ws);
+  if (c->d_cjobs) (void)hipFree(c->d_cjobs);
+  if (c->h_cjobs) (void)hipHostFree(c->h_cjobs);
+  if (c->d_cws) (void)hipFree(c->d_cws);
   if (c->d_queue) (void)hipFree(c->d_queue);
   if (c->d_first_err) (void)hipFree(c->d_first_err);
   if (c->h_poll) (void)hipHostFree(c->h_poll);
@@ -591,4 +600,65 @@ extern "C" void gmp_batch_destroy(gmp_batch* b) {
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_queue) (void)hipFree(b->d_queue);
   delete b;
+}
+
+// ---------------------------------------------------------------- compression
+extern "C" uint64_t gmp_compress_bound(uint64_t in_len) { return gmpc::bound(in_len); }
+
+extern "C" gmp_status gmp_compress_batch(gmp_ctx* c, const gmp_compress_job* h_jobs, uint32_t n_jobs,
+                                         const gmp_compress_params* p, void* stream) {
+  if (!c || !p || (n_jobs && !h_jobs)) return GMP_EINVAL;
+  if (p->window < 1 || p->window > 32768 || p->max_match < 3 || p->max_match > 258 || p->de > 1) return GMP_EINVAL;
+  uint64_t ws_total = 0;
+  for (uint32_t i = 0; i < n_jobs; i++) {
+    const gmp_compress_job& j = h_jobs[i];
+    if ((!j.d_in && j.in_len) || !j.d_out || !aligned16(j.d_out) || !j.d_out_len || !j.d_status ||
+        j.in_len > GMP_COMPRESS_MAX_BLOCK || j.out_cap < gmpc::bound(j.in_len))
+      return GMP_EINVAL;
+    ws_total += (gmpc::workspace_bytes(j.in_len) + 255) / 256 * 256;
+  }
+  if (n_jobs == 0) return GMP_OK;
+  HIP_OK(hipSetDevice(c->device));
+  if (c->pending) {
+    HIP_OK(hipEventSynchronize(c->done));
+    c->pending = false;
+  }
+  if (n_jobs > c->cjobs_cap) {
+    if (c->d_cjobs) (void)hipFree(c->d_cjobs);
+    if (c->h_cjobs) (void)hipHostFree(c->h_cjobs);
+    c->d_cjobs = nullptr;
+    c->h_cjobs = nullptr;
+    c->cjobs_cap = 0;
+    if (hipMalloc(&c->d_cjobs, n_jobs * sizeof(gmpc::CompressJob)) != hipSuccess ||
+        hipHostMalloc(&c->h_cjobs, n_jobs * sizeof(gmpc::CompressJob), hipHostMallocDefault) != hipSuccess)
+      return GMP_ENOMEM;
+    c->cjobs_cap = n_jobs;
+  }
+  if (ws_total > c->cws_cap) {
+    if (c->d_cws) (void)hipFree(c->d_cws);
+    c->d_cws = nullptr;
+    c->cws_cap = 0;
+    if (hipMalloc(&c->d_cws, ws_total) != hipSuccess) return GMP_ENOMEM;
+    c->cws_cap = ws_total;
+  }
+  uint64_t off = 0;
+  for (uint32_t i = 0; i < n_jobs; i++) {
+    const gmp_compress_job& j = h_jobs[i];
+    gmpc::CompressJob& d = c->h_cjobs[i];
+    d.in = j.d_in;
+    d.in_len = j.in_len;
+    d.out = j.d_out;
+    d.out_cap = j.out_cap;
+    d.out_len = j.d_out_len;
+    d.status = j.d_status;
+    d.ws = c->d_cws + off;
+    off += (gmpc::workspace_bytes(j.in_len) + 255) / 256 * 256;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_OK(hipMemcpyAsync(c->d_cjobs, c->h_cjobs, n_jobs * sizeof(gmpc::CompressJob), hipMemcpyHostToDevice, s));
+  gmpc::CompressParams prm{p->window, p->max_match, p->de, 0u};
+  if (gmpc_launch(c->d_cjobs, n_jobs, prm, s) != 0) return GMP_EDEVICE;
+  HIP_OK(hipEventRecord(c->done, s));
+  c->pending = true;
+  return GMP_OK;
 }

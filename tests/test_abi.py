@@ -65,3 +65,32 @@ def test_workspace_bytes_covers_token_stream(hip_lib_built):
     for n_seq, n_lit, comp in ((0, 0, 256), (1, 0, 300), (130000, 260000, 360000), (5, 1 << 20, 1 << 20)):
         ws = gmp.workspace_bytes(n_seq, n_lit, comp)
         assert ws >= 8 * n_seq + n_lit + 64 and ws % 256 == 0
+
+
+def test_host_parser_reads_byte_blocks(hip_lib_built):
+    import paper_1606_00519_amd as gmp
+    data = synth.zipf_text(300_000).tobytes()
+    for de in (0, 1):
+        blk = oracle.compress_block(data, oracle.CompressParams(block_size=1 << 20, de=de, format=1))
+        mine, ref = gmp.block_info(blk), oracle.block_info(blk)
+        assert mine["format"] == ref["format"] == 1
+        for k in ("mode", "group", "raw_len", "window", "max_match", "n_seq", "n_lit", "payload_bytes",
+                  "block_bytes"):
+            assert mine[k] == ref[k], k
+
+
+def test_compress_bound_covers_worst_cases(hip_lib_built):
+    # the largest byte-level blocks: incompressible data (literal-only records
+    # of 255) and 3-byte matches back to back
+    import numpy as np
+
+    import paper_1606_00519_amd as gmp
+    rng = np.random.default_rng(3)
+    for data in (rng.integers(0, 256, 100_000, dtype=np.uint8).tobytes(), b"abc" * 30_000, b"", b"x"):
+        blk = oracle.compress_block(data, oracle.CompressParams(block_size=1 << 20, format=1))
+        assert len(blk) <= gmp.compress_bound(len(data))
+    # a record per 3 bytes, each a match
+    n = 30_000
+    seqs = [[3, 0, 0]] + [[0, 3, 3]] * (n // 3 - 1)
+    blk = oracle.encode_byte_block(seqs, b"abc", oracle.CompressParams())
+    assert len(blk) <= gmp.compress_bound(n)
