@@ -62,12 +62,10 @@ constexpr uint32_t kStatsWords = 80, kStatsRoundBytes = 16;
 // slack; a lane that overflows makes the block fall back to one lane per
 // sub-block, which needs only the final area).
 constexpr uint32_t kPrivSlackRec = 64, kPrivSlackLit = 256;
-// per-lane extra of the segmented decoder: a log of kLogN symbol boundaries
-// on its path from its entry, spread over its whole segment (the boundaries
-// logged are at least segment bits / kLogN apart, and never closer than
-// kLogGapMin).  The tokens of a repair of the lane's start go after the lane's
-// own tokens in its area.
-constexpr uint32_t kLogN = 128, kLogGapMin = 16;
+// per-lane extra of the segmented decoder: a log of its first kLogN symbol
+// boundaries from its entry.  The tokens of a repair of the lane's start go
+// after the lane's own tokens in its area.
+constexpr uint32_t kLogN = 128;
 constexpr uint32_t kLaneExtra = 4 * kLogN;
 __host__ __device__ inline uint64_t final_bytes(uint32_t n_seq, uint32_t n_lit) { return ((8ull * n_seq + n_lit + 64 + 255) / 256) * 256; }
 __host__ __device__ inline uint64_t lane_cap_rec(uint32_t n_seq, uint32_t lanes) {

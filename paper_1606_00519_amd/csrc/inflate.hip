@@ -608,8 +608,7 @@ struct SegLane {
   uint32_t cap_rec, cap_lit;
   GMEM uint64_t* rec_out;
   GMEM uint8_t* lit_out;
-  GMEM uint32_t* log;           // literal/length symbol boundaries from the entry, >= log_gap bits apart
-  uint32_t log_gap;
+  GMEM uint32_t* log;           // the first kLogN literal/length symbol boundaries from the entry
   uint32_t overlap;             // bits decoded without output before the segment, to get into step
 };
 
@@ -726,7 +725,6 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // per sub-block tallies: records and literals since the part's start (sc0,
   // lc0), and the match bytes of those records (mlen)
   uint32_t sc = 0, lc = 0, run = 0, plen = 0, sc0 = 0, lc0 = 0, mlen = 0, nlog = 0, maybe_idx = 0, lbuf = 0;
-  uint32_t next_log = 0;  // the next boundary logged is the first at or after this bit
   // records leave two at a time (16 bytes; the area is 16-byte aligned): an
   // even-numbered record waits in rpend for the next one
   uint64_t rpend = 0;
@@ -734,7 +732,6 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
   // and log entries for the rest of theirs (lg0..lg2)
   uint32_t lw0 = 0, lw1 = 0, lw2 = 0, lg0 = 0, lg1 = 0, lg2 = 0;
   auto log_push = [&](uint32_t v) {
-    next_log = v + g.log_gap;
     const uint32_t wi = nlog & 3;
     if (wi == 3) {
       GMEM Aligned16* d = reinterpret_cast<GMEM Aligned16*>(g.log + (nlog & ~3u));
@@ -809,7 +806,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
         run = gd ? 0u : run + (gl ? 1u : 0u);
         plen = (go & is_len) ? val : plen;
         state = (go & is_len) ? 1u : 0u;
-        if (go & (state == 0) & !is_end & (nlog < kLogN) & (pos >= next_log)) log_push(pos);
+        if (go & (state == 0) & !is_end & (nlog < kLogN)) log_push(pos);
         // one exit for both ends of the loop (fewer lane masks to track)
         fail = (bad & !nudge) | over;
         over_hit |= over;
@@ -850,7 +847,7 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
       if (sb >= n_sub || pos >= g.p_end) break;
       sub_end = s_seg.sub_end[sb];
       load(pos);
-      if (nlog < kLogN && pos >= next_log) log_push(pos);
+      if (nlog < kLogN) log_push(pos);
     }
     if (!fail && sb < n_sub && (sc - sc0 | lc - lc0)) {
       atomicAdd(&s_seg.cnt_seq[sb], sc - sc0);
@@ -1369,13 +1366,13 @@ __device__ __forceinline__ void byte_record2(const LzArgs& a, uint32_t o, uint64
 // Fetcher side: stream records (1 KiB = 128 records = 2 groups per copy) and
 // literal bytes (1 KiB per copy) into their LDS rings, and compute the offsets
 // of each group from its records once they arrive.
-template <int kRes>
+template <int kRes, uint32_t kSrc>
 __device__ void fetch_tokens(const LzArgs& a) {
   const uint32_t lane = lane_id();
   const uint32_t rec_chunks = (a.n_seq + 127) / 128, lit_chunks = (a.n_lit + 1023) / 1024;
   uint32_t rf = 0, lf = 0, tf = 0, carry_out = 0, carry_lit = 0;
   StreamCursor cur;
-  if (a.rec_src == kRecLanes) cur.load(a, 0);
+  if (kSrc == kRecLanes) cur.load(a, 0);
   Spin sp(kSiteTokens);
   while (rf < rec_chunks || lf < lit_chunks) {
     uint32_t gmin = kDone;
@@ -1386,7 +1383,7 @@ __device__ void fetch_tokens(const LzArgs& a) {
     const uint32_t lit_cons = gmin < 2 * tf ? s_misc.g_lit[gmin % kGRing] : carry_lit;
     uint32_t issued = 0, gathered = 0;
     uint64_t g[8][2];
-    if (a.rec_src != kRecPacked) {
+    if (kSrc != kRecPacked) {
       // records gathered from the lane streams or the byte-level records:
       // lane l takes records 2l and 2l + 1 of up to eight 128-record chunks,
       // loads first, stores after
@@ -1396,7 +1393,7 @@ __device__ void fetch_tokens(const LzArgs& a) {
         if (ch < rec_chunks && 128ull * (ch + 1) <= 64ull * gmin + kRecRing && gathered == c) {
           const uint32_t o = 128 * ch + 2 * lane;
           if (o < a.n_seq) {
-            if (a.rec_src == kRecByte) byte_record2(a, o, g[c][0], g[c][1]);
+            if (kSrc == kRecByte) byte_record2(a, o, g[c][0], g[c][1]);
             else cur.record2(a, o, g[c][0], g[c][1]);
           } else {
             g[c][0] = g[c][1] = 0ull;
@@ -1530,7 +1527,7 @@ __device__ void spill_append(const LzArgs& a, bool spilled, uint32_t dst, uint32
 }
 
 // Resolver wavefront w of kRes.
-template <int kRes>
+template <int kRes, bool kSpill>
 __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
   uint8_t* ring = ring_ptr();
   const uint32_t lane = lane_id();
@@ -1599,7 +1596,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
                    (M0 == 0 || (D >= M0 && (src0 & kRingMask) + ((M0 + 15) & ~15u) <= kRing)) &&
                    (L == 0 || (lsrc & (kLitRing - 1)) + ((L + 15) & ~15u) <= kLitRing));
     const bool plain = !__ballot(!lane_plain);
-    const bool spill_mode = a.spill && a.res == kResMRR;
+    const bool spill_mode = kSpill && a.res == kResMRR;
     if (fast) {
       if (!wait_window(g_end)) break;
       if (spill_mode) pend_clear(g_out, g_end, lane);
@@ -1940,7 +1937,6 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.rec_out = (GMEM uint64_t*)(priv + lane_bytes * t);
     g.lit_out = priv + lane_bytes * t + 8 * cap_rec;
     g.log = (GMEM uint32_t*)(g.lit_out + cap_lit);
-    g.log_gap = max(kLogGapMin, (g.p_end - g.p_begin + kLogN - 1) / kLogN);
     sh.sub_woff[t] = g.base_word;
     sh.sub_nw[t] = g.n_words;
     sh.rd[t] = 0;
@@ -2100,11 +2096,14 @@ __device__ void resolve_phase(const LzArgs& a) {
   if (t < kMaxDecWaves) sh.next_group[t] = t < (uint32_t)kRes ? t : kDone;
   __syncthreads();
   if (wave == kDec) {
-    fetch_tokens<kRes>(a);
+    if (a.rec_src == kRecLanes) fetch_tokens<kRes, kRecLanes>(a);
+    else if (a.rec_src == kRecByte) fetch_tokens<kRes, kRecByte>(a);
+    else fetch_tokens<kRes, kRecPacked>(a);
   } else if (wave == flusher_wave<kDec>()) {
     flush_output(a);
   } else if (wave < (uint32_t)kRes) {
-    resolve_groups<kRes>(a, wave);
+    if (a.spill) resolve_groups<kRes, true>(a, wave);
+    else resolve_groups<kRes, false>(a, wave);
   }
   __syncthreads();
   // the spill list's length (none after an error: the block has failed)
@@ -2178,8 +2177,11 @@ __device__ int check_byte_records(const GMEM uint8_t* recs, uint32_t n_seq, uint
 // records are read straight from the compressed block, so decoding and LZ77
 // decompression are one pass): header checks, record checks, then A3-A6 with
 // the fetcher gathering the records from the block.
+// Returns kOK with `a` set for A3-A6, kBlockDone for a block with nothing to
+// resolve, or an error.
+constexpr int kBlockDone = 1;
 template <int kDec, int kMode>
-__device__ int inflate_byte_block(const DevJob& job, uint32_t flags) {
+__device__ __forceinline__ int prepare_byte_block(const DevJob& job, uint32_t flags, LzArgs& a) {
   constexpr uint32_t kThreads = block_threads<kDec>();
   Misc& sh = s_misc;
   const GMEM uint8_t* blk = gmem(job.comp);
@@ -2203,7 +2205,6 @@ __device__ int inflate_byte_block(const DevJob& job, uint32_t flags) {
   if (threadIdx.x == 0) sh.a2_path = 3;
   stamp(job, 1);
   stamp(job, 2);
-  LzArgs a;
   a.rec_src = kRecByte;
   a.recs = blk + kByteHdr;
   a.recs_len = rec_bytes;
@@ -2220,36 +2221,17 @@ __device__ int inflate_byte_block(const DevJob& job, uint32_t flags) {
   a.max_rounds = (flags & GMPK_ROUNDS_MASK) >> GMPK_ROUNDS_SHIFT;
   a.spill = a.max_rounds && job.spill ? (GMEM uint32_t*)(gmem(job.spill) + 16) : nullptr;
   a.priv = nullptr;
-  if (n_seq) resolve_phase<kDec>(a);
-  stamp(job, 3);
-  return sh.abort ? kESTALL : (sh.err ? sh.err : kOK);
+  return n_seq ? kOK : kBlockDone;
 }
 
-// Decodes one block and returns its status (the same value in every thread).
-// kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR,
-// GMPK_MODE_DE or GMPK_MODE_SC.
+// A0-A2 of a Gompresso/Bit block: returns kOK with `a` set for A3-A6,
+// kBlockDone for an empty block, or an error.
 template <int kDec, int kMode>
-__device__ int inflate_block(const DevJob& job, uint32_t flags) {
+__device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t flags, LzArgs& a) {
   constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
-  stamp(job, 0);
-  if (t == 0) {
-    sh.err = 0;
-    sh.abort = 0;
-    sh.n_split = 0;
-    sh.n_de_rounds = 0;
-    sh.a2_path = 0;
-    sh.n_repaired = 0;
-    sh.stall_site = 0;
-    sh.seg_reject = 0;
-    sh.seg_retry = 0;
-    sh.spill_n = 0;
-  }
-  if (t < 64) sh.rbytes[t] = 0;
-  __syncthreads();
   const GMEM uint8_t* blk = gmem(job.comp);
-  if (job.comp_len >= 4 && ld32(blk) == kMagicByte) return inflate_byte_block<kDec, kMode>(job, flags);
   // ---- A0: header
   int err = kOK;
   uint32_t mode = 0, group = 0, lmax = 0, raw_len = 0, window = 0, max_match = 0, n_sub = 0, n_seq = 0,
@@ -2289,7 +2271,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   if (err != kOK) return err;
   if (n_sub == 0) {
     // an empty block: nothing to decode
-    return (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kOK : kEFORMAT;
+    return (raw_len == 0 && n_seq == 0 && n_lit == 0 && payload == 0) ? kBlockDone : kEFORMAT;
   }
   // ---- A1: code lengths and lookup tables
   for (uint32_t i = t; i < kNumLL + kNumD; i += kThreads) sh.lens[i] = (blk[32 + i / 2] >> ((i & 1) * 4)) & 15;
@@ -2308,17 +2290,19 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   const GMEM uint8_t* payload_bytes = blk + kHdrBytes + kIdxBytes * n_sub + 16;
   GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
   GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
-  bool segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
-                                          max_match, ws_seq, ws_lit, kOverlapBits);
   // Lanes that stayed out of step past what their repair covers (codes that
-  // fall into step slowly): a second attempt with a far longer warm-up costs
-  // less than decoding every sub-block in one lane.
-  __syncthreads();  // the rejection reasons are in LDS for every thread
-  if (!segmented && (sh.seg_reject & (kRejMeet | kRejRepair)) && !(sh.seg_reject & (kRejIndex | kRejCode)) &&
-      !sh.abort) {
-    if (t == 0) sh.seg_retry = 1;
+  // fall into step slowly) get a second attempt with a far longer warm-up:
+  // it costs less than decoding every sub-block in one lane.
+  bool segmented = false;
+#pragma nounroll
+  for (uint32_t attempt = 0; attempt < 2; attempt++) {
     segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
-                                       max_match, ws_seq, ws_lit, kOverlapRetry);
+                                       max_match, ws_seq, ws_lit, attempt ? kOverlapRetry : kOverlapBits);
+    __syncthreads();  // the rejection reasons are in LDS for every thread
+    if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & (kRejIndex | kRejCode)) ||
+        sh.abort)
+      break;
+    if (t == 0) sh.seg_retry = 1;
   }
   uint32_t carry[4] = {0, 0, 0, 0};
   for (uint32_t c = 0; !segmented && c < n_sub; c += kLanes) {
@@ -2378,9 +2362,8 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
   __syncthreads();  // workspace writes of all lanes are visible after this barrier
   if (sh.err || sh.abort) return sh.abort ? kESTALL : sh.err;
   stamp(job, 2);
-  // ---- A3-A6: the decoder wavefronts resolve, the fetcher stages tokens,
-  // the last wavefront writes the output
-  LzArgs a;
+  // ---- A3-A6 (next): the decoder wavefronts resolve, the fetcher stages
+  // tokens, the last wavefront writes the output
   a.rec_src = segmented ? kRecLanes : kRecPacked;
   a.recs = gmem(job.ws);
   a.recs_len = job.ws_len;
@@ -2403,6 +2386,36 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     a.lane_bytes = 8 * cap_rec + cap_lit + kLaneExtra;
     a.lanes = kLanes;
   }
+  return kOK;
+}
+
+// Decodes one block and returns its status (the same value in every thread).
+// kMode: GMPK_MODE_AUTO (per block from its header), GMPK_MODE_MRR,
+// GMPK_MODE_DE or GMPK_MODE_SC.  Both formats meet at one A3-A6 call.
+template <int kDec, int kMode>
+__device__ int inflate_block(const DevJob& job, uint32_t flags) {
+  Misc& sh = s_misc;
+  const uint32_t t = threadIdx.x;
+  stamp(job, 0);
+  if (t == 0) {
+    sh.err = 0;
+    sh.abort = 0;
+    sh.n_split = 0;
+    sh.n_de_rounds = 0;
+    sh.a2_path = 0;
+    sh.n_repaired = 0;
+    sh.stall_site = 0;
+    sh.seg_reject = 0;
+    sh.seg_retry = 0;
+    sh.spill_n = 0;
+  }
+  if (t < 64) sh.rbytes[t] = 0;
+  __syncthreads();
+  LzArgs a;
+  const int st = job.comp_len >= 4 && ld32(gmem(job.comp)) == kMagicByte
+                     ? prepare_byte_block<kDec, kMode>(job, flags, a)
+                     : prepare_bit_block<kDec, kMode>(job, flags, a);
+  if (st != kOK) return st == kBlockDone ? kOK : st;
   resolve_phase<kDec>(a);
   stamp(job, 3);
   return sh.abort ? kESTALL : (sh.err ? sh.err : kOK);

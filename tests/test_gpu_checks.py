@@ -264,10 +264,10 @@ def test_piecewise_group_keeps_done_mark_monotonic(ctx, waves):
 def test_slow_sync_blocks_decode_in_segments(ctx):
     # DE streams of the CSV rows hold codes that fall into step slowly: in
     # these 2 MiB blocks some decoder lanes (of 448) stay out of step for
-    # 6-8 kbit past their segment's start.  Each lane's boundary log spans its
-    # whole segment and a repair's tokens go after the lane's own, so the
-    # repair from the previous lane's exit covers them and the blocks are
-    # decoded in segments.
+    # 6-8 kbit past their segment's start, beyond what the first attempt's
+    # boundary log covers.  The blocks are then decoded in segments a second
+    # time, each lane starting 8 kbit before its segment, rather than one lane
+    # per sub-block.
     n = 2 << 20
     blocks, raws = [], []
     for b in (47, 55):
@@ -280,3 +280,4 @@ def test_slow_sync_blocks_decode_in_segments(ctx):
     print(f"[gpu] paths {[int(c[0]) for c in cnt]}, second attempts {[int(c[7]) for c in cnt]}, "
           f"rejections {[int(c[6]) for c in cnt]}", flush=True)
     assert all(c[0] == 1 for c in cnt)
+    assert any(c[7] == 1 for c in cnt)
