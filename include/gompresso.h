@@ -104,6 +104,12 @@ typedef int32_t gmp_status;
                                  destination of the group's first back-reference.  Without the flag a group
                                  that breaks the rule is still decoded correctly (by rounds); with it the
                                  block's status is GMP_EDIST, as the CPU format check reports */
+#define GMP_FLAG_PLAIN_MRR 0x400u /* MRR exactly as section "Multi-Round Resolution (MRR)" states it.  By
+                                 default a back-reference that does not overlap its own output and reads
+                                 only bytes that an earlier such back-reference of its group writes first
+                                 reads that one's source instead (at most two such moves, groups of at most
+                                 32 KiB of output): the same bytes, available in an earlier round.  Output
+                                 is identical either way; only the round counts differ */
 
 typedef struct gmp_ctx gmp_ctx;
 typedef struct gmp_batch gmp_batch;

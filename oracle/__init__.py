@@ -103,6 +103,8 @@ def lib():
         L.gmpref_validate_block.argtypes = [u8p, C.c_size_t]
         L.gmpref_de_holds.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32]
         L.gmpref_mrr_rounds.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p]
+        L.gmpref_mrr_rounds_redirect.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint64,
+                                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gmpref_limited_lengths.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         L.gmpref_canonical_codes.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.gmpref_length_table.argtypes = [C.c_void_p, C.c_void_p]
@@ -112,7 +114,8 @@ def lib():
         for fn in ("gmpref_compress", "gmpref_compress_block", "gmpref_parse_block", "gmpref_encode_block",
                    "gmpref_block_info_parse", "gmpref_decompress_block", "gmpref_decompress",
                    "gmpref_block_tokens", "gmpref_lz77_expand", "gmpref_validate_block", "gmpref_de_holds",
-                   "gmpref_mrr_rounds", "gmpref_limited_lengths", "gmpref_canonical_codes"):
+                   "gmpref_mrr_rounds", "gmpref_mrr_rounds_redirect", "gmpref_limited_lengths",
+                   "gmpref_canonical_codes"):
             getattr(L, fn).restype = C.c_int
         L.gmpref_free.restype = None
         _lib = L
@@ -323,6 +326,25 @@ def mrr_rounds(seqs, group: int):
     rc = lib().gmpref_mrr_rounds(s.ctypes.data, s.shape[0], group, rounds.ctypes.data, bpr.ctypes.data)
     if rc:
         raise OracleError(rc, "mrr_rounds")
+    return rounds[:ng], bpr
+
+
+def mrr_rounds_redirect(seqs, group: int, jumps: int = 2, span_limit: int = 32768, per_seq: bool = False):
+    """MRR rounds with sources moved through the group's own non-overlapping
+    copies first (gmpref_mrr_rounds_redirect): (rounds per group, bytes per
+    round), and with per_seq also (round of each sequence, distance it reads)."""
+    s = _seq_array(seqs)
+    ng = (s.shape[0] + group - 1) // group
+    rounds = np.zeros(max(ng, 1), np.uint32)
+    bpr = np.zeros(group, np.uint64)
+    sr = np.zeros(max(s.shape[0], 1), np.uint32)
+    sd = np.zeros(max(s.shape[0], 1), np.uint32)
+    rc = lib().gmpref_mrr_rounds_redirect(s.ctypes.data, s.shape[0], group, jumps, C.c_uint64(span_limit),
+                                          rounds.ctypes.data, bpr.ctypes.data, sr.ctypes.data, sd.ctypes.data)
+    if rc:
+        raise OracleError(rc, "mrr_rounds_redirect")
+    if per_seq:
+        return rounds[:ng], bpr, sr[:s.shape[0]], sd[:s.shape[0]]
     return rounds[:ng], bpr
 
 

@@ -1078,23 +1078,60 @@ int gmpref_validate_block(const uint8_t* blk, size_t len) {
    its own output after that.  Returns rounds per group and bytes per round. */
 int gmpref_mrr_rounds(const gmpref_seq* seqs, size_t n_seq, uint32_t G, uint32_t* rounds,
                       uint64_t* bytes_per_round) {
+  return gmpref_mrr_rounds_redirect(seqs, n_seq, G, 0, 0, rounds, bytes_per_round, NULL, NULL);
+}
+
+/* The same, where each back-reference that does not overlap itself first
+   moves its source, up to `jumps` times, through the group's own copies: if
+   the bytes it reads all lie inside the destination of an earlier sequence k
+   of the group (the last one whose destination starts at or before them)
+   whose back-reference does not overlap itself either, those bytes equal the
+   ones dist_k further back, so the source moves there (while it still lies
+   inside the group's output).  Only groups whose output is at most
+   span_limit bytes (0: any) are redirected.  Byte output is unchanged; the
+   rounds can only fall.  seq_round / seq_dist (optional) receive each
+   sequence's round (0: no back-reference) and the distance it reads from. */
+int gmpref_mrr_rounds_redirect(const gmpref_seq* seqs, size_t n_seq, uint32_t G, uint32_t jumps,
+                               uint64_t span_limit, uint32_t* rounds, uint64_t* bytes_per_round,
+                               uint32_t* seq_round, uint32_t* seq_dist) {
   if (G == 0 || G > 1024) return GMPREF_EINVAL;
   uint64_t* dst = (uint64_t*)malloc(sizeof(uint64_t) * G);
+  uint64_t* src = (uint64_t*)malloc(sizeof(uint64_t) * G);
   int* pend = (int*)malloc(sizeof(int) * G);
   int* done_now = (int*)malloc(sizeof(int) * G);
-  if (!dst || !pend || !done_now) { free(dst); free(pend); free(done_now); return GMPREF_ENOMEM; }
+  if (!dst || !src || !pend || !done_now) {
+    free(dst); free(src); free(pend); free(done_now);
+    return GMPREF_ENOMEM;
+  }
   for (uint32_t r = 0; r < G; r++) bytes_per_round[r] = 0;
   uint64_t pos = 0;
   size_t g = 0;
   for (size_t g0 = 0; g0 < n_seq; g0 += G, g++) {
     size_t m = (g0 + G < n_seq) ? G : n_seq - g0;
     int npend = 0;
+    const uint64_t g_start = pos;
     for (size_t i = 0; i < m; i++) {
       pos += seqs[g0 + i].lit_len;
       dst[i] = pos;
+      src[i] = pos - seqs[g0 + i].dist;
       pos += seqs[g0 + i].match_len;
       pend[i] = seqs[g0 + i].match_len > 0;
       npend += pend[i];
+    }
+    if (jumps && (span_limit == 0 || pos - g_start <= span_limit)) {
+      for (size_t i = 0; i < m; i++) {
+        const uint64_t L = seqs[g0 + i].match_len;
+        if (L == 0 || seqs[g0 + i].dist < L) continue;
+        for (uint32_t j = 0; j < jumps && src[i] >= g_start; j++) {
+          size_t k = m;  /* the last sequence whose destination starts at or before the source */
+          for (size_t q = 0; q < m; q++)
+            if (dst[q] <= src[i]) k = q;
+          if (k == m) break;
+          const uint64_t Lk = seqs[g0 + k].match_len, dk = seqs[g0 + k].dist;
+          if (Lk == 0 || dk < Lk || src[i] + L > dst[k] + Lk) break;
+          src[i] -= dk;
+        }
+      }
     }
     uint32_t nr = 0;
     while (npend > 0) {
@@ -1104,8 +1141,8 @@ int gmpref_mrr_rounds(const gmpref_seq* seqs, size_t n_seq, uint32_t G, uint32_t
       for (size_t i = 0; i < m; i++) {
         done_now[i] = 0;
         if (!pend[i]) continue;
-        uint64_t d = seqs[g0 + i].dist, L = seqs[g0 + i].match_len;
-        uint64_t need_end = dst[i] - d + (L < d ? L : d);
+        uint64_t d = dst[i] - src[i], L = seqs[g0 + i].match_len;
+        uint64_t need_end = src[i] + (L < d ? L : d);
         if (need_end <= hwm) done_now[i] = 1;
       }
       for (size_t i = 0; i < m; i++)
@@ -1113,12 +1150,18 @@ int gmpref_mrr_rounds(const gmpref_seq* seqs, size_t n_seq, uint32_t G, uint32_t
           pend[i] = 0;
           npend--;
           bytes_per_round[nr] += seqs[g0 + i].match_len;
+          if (seq_round) seq_round[g0 + i] = nr + 1;
         }
       nr++;
+    }
+    for (size_t i = 0; i < m; i++) {
+      if (seq_round && seqs[g0 + i].match_len == 0) seq_round[g0 + i] = 0;
+      if (seq_dist) seq_dist[g0 + i] = (uint32_t)(dst[i] - src[i]);
     }
     rounds[g] = nr;
   }
   free(dst);
+  free(src);
   free(pend);
   free(done_now);
   return GMPREF_OK;

@@ -192,6 +192,15 @@ int gmpref_de_holds(const gmpref_seq* seqs, size_t n_seq, uint32_t G);
  * rounds[g] for g < ceil(n_seq/G); bytes_per_round[r] for r in 0..G-1 (round r+1). */
 int gmpref_mrr_rounds(const gmpref_seq* seqs, size_t n_seq, uint32_t G,
                       uint32_t* rounds, uint64_t* bytes_per_round);
+/* MRR rounds where each back-reference that does not overlap itself first moves
+ * its source, up to `jumps` times, through an earlier non-overlapping copy of
+ * its own group whose destination holds every byte it reads (groups whose
+ * output exceeds span_limit bytes are not redirected; 0 = no limit).
+ * seq_round / seq_dist may be NULL; else n_seq entries each: the round of each
+ * sequence's back-reference (0 if it has none) and the distance it reads from. */
+int gmpref_mrr_rounds_redirect(const gmpref_seq* seqs, size_t n_seq, uint32_t G, uint32_t jumps,
+                               uint64_t span_limit, uint32_t* rounds, uint64_t* bytes_per_round,
+                               uint32_t* seq_round, uint32_t* seq_dist);
 
 /* ---- Huffman helpers exposed for pinning ------------------------------ */
 /* Optimal code lengths limited to lmax (package-merge); zero weight -> 0. */

@@ -28,6 +28,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 MODE_AUTO, MODE_MRR, MODE_DE, MODE_SC = 0, 1, 2, 3
 FLAG_STATS = 0x100
 FLAG_VERIFY_DE = 0x200
+FLAG_PLAIN_MRR = 0x400
 # per-block counters (gmp_job.d_stats)
 STATS_WORDS = 80
 (STAT_A2_PATH, STAT_REPAIRED, STAT_GROUPS, STAT_SPLIT, STAT_DE_ROUNDS, STAT_STALL_SITE, STAT_SEG_REJECT,

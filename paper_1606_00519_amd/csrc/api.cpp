@@ -270,7 +270,12 @@ gmp_status ctx_launch(gmp_ctx* c, size_t n_jobs, uint32_t flags, hipStream_t s) 
   return GMP_OK;
 }
 
-bool valid_flags(uint32_t flags) { return (flags & ~(GMP_MODE_MASK | GMP_FLAG_STATS | GMP_FLAG_VERIFY_DE)) == 0; }
+static_assert(GMP_FLAG_STATS == GMPK_FLAG_STATS && GMP_FLAG_VERIFY_DE == GMPK_FLAG_VERIFY_DE &&
+                  GMP_FLAG_PLAIN_MRR == GMPK_FLAG_PLAIN_MRR,
+              "the kernels take the API's flags as they are");
+bool valid_flags(uint32_t flags) {
+  return (flags & ~(GMP_MODE_MASK | GMP_FLAG_STATS | GMP_FLAG_VERIFY_DE | GMP_FLAG_PLAIN_MRR)) == 0;
+}
 
 // Device blocks are read with 16-byte asynchronous copies into LDS.
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }

@@ -10,6 +10,7 @@
 #define GMPK_MODE_MASK 3u
 #define GMPK_FLAG_STATS 0x100u
 #define GMPK_FLAG_VERIFY_DE 0x200u
+#define GMPK_FLAG_PLAIN_MRR 0x400u
 // Multi-round resolution over several launches: the first launch resolves at
 // most R rounds per group of 64 sequences (R in bits 16-23 of the kernel's
 // flags; 0 = every round), writing the back-references still pending to the

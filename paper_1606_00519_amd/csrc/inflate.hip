@@ -1270,6 +1270,7 @@ struct LzArgs {
   uint32_t max_rounds;
   GMEM uint32_t* spill;  // list A: {destination, distance << 9 | length} entries (null: no spilling)
   bool verify_de;    // a DE group that breaks the DE rule is an error (it is resolved by rounds either way)
+  bool redirect;     // MRR: sources moved through the group's own copies first (see resolve_groups)
   bool stats;        // count bytes per round, split groups and DE groups resolved by rounds
   GMEM uint8_t* rounds;
   // kRecLanes: the segmented decoder's lane areas (priv: the first area)
@@ -1544,7 +1545,7 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
     const uint32_t g_out = s_misc.g_out[g % kGRing], g_lit = s_misc.g_lit[g % kGRing];
     uint32_t L = rec.x;
     const uint32_t M0 = rec.y & 0xFFFFu;
-    const uint32_t D = rec.y >> 16;
+    uint32_t D = rec.y >> 16;
     // A3: two exclusive prefix sums over the group's sequences
     const uint32_t inc_lit = wave_incl_scan(L);
     const uint32_t inc_out = wave_incl_scan(L + M0);
@@ -1585,6 +1586,35 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
           one_pass = false;
         }
       }
+    }
+    // MRR: a back-reference that does not overlap itself and whose bytes all
+    // lie inside the destination of an earlier such copy of the group (the
+    // last lane whose destination starts at or before its source) reads that
+    // copy's source instead: the same bytes, available a round earlier.  Up to
+    // kJumps moves, while the source is still inside the group's output; not
+    // for groups larger than the on-chip span (their pieces could not reach
+    // so far back).  D becomes the distance to the final source.
+    if (a.res == kResMRR && a.redirect && g_end - g_out <= kSpanCap) {
+      constexpr uint32_t kJumps = 2;
+      const uint32_t dst0 = pos + L;
+      const bool cand = valid && M > 0 && D >= M;
+      uint32_t s = dst0 - D;
+      for (uint32_t j = 0; j < kJumps; j++) {
+        const bool in_group = cand && s >= g_out;
+        if (!__ballot(in_group)) break;
+        int idx = -1;  // the last lane whose destination starts at or before s
+        for (uint32_t step = 64; step; step >>= 1) {
+          const int c = idx + (int)step;
+          const uint32_t dc = shfl(dst0, (uint32_t)min(c, 63));
+          if (c < 64 && dc <= s) idx = c;
+        }
+        const uint32_t ii = idx < 0 ? 0u : (uint32_t)idx;
+        const uint32_t di = shfl(dst0, ii), mi = shfl(M, ii), Di = shfl(D, ii);
+        const bool ok = in_group && idx >= 0 && mi > 0 && Di >= mi && s + M <= di + mi;
+        if (!__ballot(ok)) break;
+        s = ok ? s - Di : s;
+      }
+      D = cand ? dst0 - s : D;
     }
     // fast path: the group's literals are staged and its output fits the
     // window; "plain" when moreover no copy wraps around the ring or the
@@ -2216,6 +2246,7 @@ __device__ __forceinline__ int prepare_byte_block(const DevJob& job, uint32_t fl
   a.raw_len = raw_len;
   a.res = kMode == GMPK_MODE_SC ? kResSC : (single_pass ? kResDE : kResMRR);
   a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
+  a.redirect = (flags & GMPK_FLAG_PLAIN_MRR) == 0;
   a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
   a.max_rounds = (flags & GMPK_ROUNDS_MASK) >> GMPK_ROUNDS_SHIFT;
@@ -2375,6 +2406,7 @@ __device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t fla
   a.raw_len = raw_len;
   a.res = kMode == GMPK_MODE_SC ? kResSC : (single_pass ? kResDE : kResMRR);
   a.verify_de = (flags & GMPK_FLAG_VERIFY_DE) != 0;
+  a.redirect = (flags & GMPK_FLAG_PLAIN_MRR) == 0;
   a.stats = (flags & GMPK_FLAG_STATS) && job.stats;
   a.rounds = (flags & GMPK_FLAG_STATS) && job.rounds ? gmem(job.rounds) : nullptr;
   a.max_rounds = (flags & GMPK_ROUNDS_MASK) >> GMPK_ROUNDS_SHIFT;

@@ -42,7 +42,7 @@ extern "C" gmp_status gmp_decompress_block_noalloc(const uint8_t* d_block, size_
                                                    size_t h_len, uint8_t* d_out, size_t out_len, int32_t* d_status,
                                                    uint32_t flags, void* stream) {
   if (!d_block || !h_block || !d_status) return GMP_EINVAL;
-  if ((flags & ~(GMP_MODE_MASK | GMP_FLAG_VERIFY_DE)) != 0) return GMP_EINVAL;
+  if ((flags & ~(GMP_MODE_MASK | GMP_FLAG_VERIFY_DE | GMP_FLAG_PLAIN_MRR)) != 0) return GMP_EINVAL;
   if (reinterpret_cast<uintptr_t>(d_block) & 15) return GMP_EINVAL;
   gmp_block_info info;
   gmp_status st = gmp_block_info_parse(h_block, h_len, &info);

@@ -353,7 +353,7 @@ extern "C" gmp_status gmp_server_create(gmp_ctx* ctx, uint64_t budget_bytes, uin
 extern "C" gmp_status gmp_server_submit(gmp_server* s, const gmp_request* req) {
   if (!s || !req || !req->d_stream || !req->h_stream || !req->d_status) return GMP_EINVAL;
   const uint32_t mode = req->flags & GMP_MODE_MASK;
-  if ((req->flags & ~(GMP_MODE_MASK | GMP_FLAG_VERIFY_DE)) != 0) return GMP_EINVAL;
+  if ((req->flags & ~(GMP_MODE_MASK | GMP_FLAG_VERIFY_DE | GMP_FLAG_PLAIN_MRR)) != 0) return GMP_EINVAL;
   if (reinterpret_cast<uintptr_t>(req->d_stream) & 15) return GMP_EINVAL;
   const uint8_t* hs = static_cast<const uint8_t*>(req->h_stream);
   if (req->len < 32 || rd32(hs) != kMagicStream) return GMP_EFORMAT;

@@ -101,31 +101,38 @@ def test_byte_random_tokens(ctx, seed, overlap):
 
 @pytest.mark.parametrize("k", [1, 2, 4, 8])
 @pytest.mark.parametrize("waves", [1, 7])
-def test_byte_nesting_rounds(ctx, k, waves):
-    # k interleaved chains of 16-byte back-references: 64/k rounds in every group
+@pytest.mark.parametrize("plain", [True, False])
+def test_byte_nesting_rounds(ctx, k, waves, plain):
+    # k interleaved chains of 16-byte back-references: 64/k rounds in every
+    # group by the paper's rule, a third of that with sources moved twice
+    import paper_1606_00519_amd as gmp
     seqs, lits = synth.nesting_tokens(64 * 16, k, str_len=16)
     blk = oracle.encode_byte_block(seqs, lits, P())
     rc, want = oracle.decompress_block(blk)
     assert rc == 0
     cnt = []
-    st, outs, rounds = decode_batch(ctx, [blk], flags=1, stats=True, waves=waves, counters=cnt)
+    st, outs, rounds = decode_batch(ctx, [blk], flags=1 | (gmp.FLAG_PLAIN_MRR if plain else 0), stats=True,
+                                    waves=waves, counters=cnt)
     assert st[0] == 0 and outs[0] == want
-    want_rounds, bpr = oracle.mrr_rounds(seqs, 64)
-    assert rounds[0].tolist() == want_rounds.tolist() == [64 // k] * 16
+    want_rounds, bpr = (oracle.mrr_rounds if plain else oracle.mrr_rounds_redirect)(seqs, 64)
+    assert rounds[0].tolist() == want_rounds.tolist() == [64 // k if plain else -(-(64 // k) // 3)] * 16
     assert cnt[0][0] == 3                                   # no Huffman stage
     assert cnt[0][16:16 + 64].tolist() == bpr[:64].tolist()
 
 
 @pytest.mark.parametrize("waves", [1, 7])
-def test_byte_real_data_rounds(ctx, waves):
+@pytest.mark.parametrize("plain", [True, False])
+def test_byte_real_data_rounds(ctx, waves, plain):
+    import paper_1606_00519_amd as gmp
     data = synth.zipf_text(2 << 20).tobytes()
     blocks = [oracle.compress_block(data[i:i + (1 << 20)], P(block_size=1 << 20)) for i in (0, 1 << 20)]
     cnt = []
-    st, outs, rounds = decode_batch(ctx, blocks, flags=1, stats=True, waves=waves, counters=cnt)
+    st, outs, rounds = decode_batch(ctx, blocks, flags=1 | (gmp.FLAG_PLAIN_MRR if plain else 0), stats=True,
+                                    waves=waves, counters=cnt)
     assert np.all(st == 0) and b"".join(outs) == data
     for b, r, c in zip(blocks, rounds, cnt):
         rc, seqs, _ = oracle.block_tokens(b)
-        want, bpr = oracle.mrr_rounds(seqs, 64)
+        want, bpr = (oracle.mrr_rounds if plain else oracle.mrr_rounds_redirect)(seqs, 64)
         assert (r & 0x7F).tolist() == want.tolist()
         assert c[16:80].tolist() == bpr[:64].tolist()
 

@@ -25,7 +25,7 @@ def ctx(hip_lib_built):
     c.close()
 
 
-def run(ctx, blocks, rounds, waves=7, persistent=False, graph=False, stats=False, runs=1):
+def run(ctx, blocks, rounds, waves=7, persistent=False, graph=False, stats=False, runs=1, plain=False):
     """Decode `blocks` with one batch at `rounds` rounds per launch; returns
     (status, outputs, per-block counters)."""
     import torch
@@ -53,7 +53,7 @@ def run(ctx, blocks, rounds, waves=7, persistent=False, graph=False, stats=False
     print(f"[gpu] multi-launch blocks={len(blocks)} rounds={rounds} waves={waves} persistent={persistent} "
           f"graph={graph}", flush=True)
     batch = ctx.batch_create(jobs, status)
-    flags = gmp.MODE_MRR | (gmp.FLAG_STATS if stats else 0)
+    flags = gmp.MODE_MRR | (gmp.FLAG_STATS if stats else 0) | (gmp.FLAG_PLAIN_MRR if plain else 0)
     if graph:
         batch.graph_create(flags, waves=waves, persistent=persistent, workgroups=0, rounds_per_launch=rounds)
         for _ in range(runs):
@@ -77,10 +77,13 @@ def run(ctx, blocks, rounds, waves=7, persistent=False, graph=False, stats=False
 @pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("k", [1, 4, 16])
 @pytest.mark.parametrize("rounds", [1, 4, 16, 0])
-def test_nesting_spill_counts(ctx, fmt, k, rounds):
-    # k interleaved chains: every group of 64 takes 64/k rounds.  With R <
-    # 64/k rounds per launch the first group resolves R*k back-references and
-    # every later one reads bytes left pending, so exactly n - R*k are spilled.
+@pytest.mark.parametrize("plain", [True, False])
+def test_nesting_spill_counts(ctx, fmt, k, rounds, plain):
+    # k interleaved chains: every group of 64 takes 64/k rounds by the paper's
+    # rule.  With R < 64/k rounds per launch the first group resolves R*k
+    # back-references and every later one reads bytes left pending, so exactly
+    # n - R*k are spilled.  With sources moved twice through each chain a
+    # group takes ceil(64/k / 3) rounds and its first 3 R k copies resolve.
     n = 64 * 12
     seqs, lits = synth.nesting_tokens(n, k, str_len=16)
     if fmt:
@@ -92,11 +95,12 @@ def test_nesting_spill_counts(ctx, fmt, k, rounds):
         blk = oracle.encode_block(seqs, lits, [len(seqs)], oracle.CompressParams())
     rc, want = oracle.decompress_block(blk)
     assert rc == 0
-    st, outs, cnt = run(ctx, [blk], rounds, stats=True)
+    st, outs, cnt = run(ctx, [blk], rounds, stats=True, plain=plain)
     assert st[0] == 0 and outs[0] == want
     if fmt == 0:
         spilled = int(cnt[0][8])
-        expect = n - rounds * k if 0 < rounds < 64 // k else 0
+        per_group, done = (64 // k, rounds * k) if plain else (-(-(64 // k) // 3), 3 * rounds * k)
+        expect = n - done if 0 < rounds < per_group else 0
         assert spilled == expect
 
 
@@ -116,7 +120,7 @@ def test_real_data(ctx, rounds, waves, persistent):
     # groups needs more rounds than one launch does (the oracle's simulator)
     for b, c in zip(blocks, cnt):
         rc, seqs, _ = oracle.block_tokens(b)
-        max_r = int(oracle.mrr_rounds(seqs, 64)[0].max())
+        max_r = int(oracle.mrr_rounds_redirect(seqs, 64)[0].max())
         assert (c[8] > 0) == (max_r > rounds), (max_r, int(c[8]))
 
 

@@ -151,30 +151,42 @@ def test_overlap_distances(ctx, dist):
 
 @pytest.mark.parametrize("waves", [1, 7])
 @pytest.mark.parametrize("k", [1, 2, 4, 8])
-def test_mrr_rounds_nesting(ctx, k, waves):
+@pytest.mark.parametrize("plain", [True, False])
+def test_mrr_rounds_nesting(ctx, k, waves, plain):
+    import paper_1606_00519_amd as gmp
     seqs, lits = synth.nesting_tokens(64 * 40, k, str_len=16)
     blk = oracle.encode_block(seqs, lits, [len(seqs) // 2, len(seqs) - len(seqs) // 2], P())
-    want_rounds, want_bytes = oracle.mrr_rounds(seqs, 64)
+    if plain:       # the paper's rule: 64/k rounds
+        want_rounds, want_bytes = oracle.mrr_rounds(seqs, 64)
+        per_group = 64 // k
+    else:           # sources moved through the chain twice: a third of them
+        want_rounds, want_bytes = oracle.mrr_rounds_redirect(seqs, 64)
+        per_group = -(-(64 // k) // 3)
     cnt = []
-    st, outs, rounds = decode_batch(ctx, [blk], flags=1, stats=True, waves=waves, counters=cnt)
+    st, outs, rounds = decode_batch(ctx, [blk], flags=1 | (gmp.FLAG_PLAIN_MRR if plain else 0), stats=True,
+                                    waves=waves, counters=cnt)
     assert st[0] == 0 and outs[0] == oracle.decompress_block(blk)[1]
-    assert rounds[0].tolist() == want_rounds.tolist() == [64 // k] * 40
-    # bytes copied per round, summed over groups: the simulator's, and 16 k bytes per round per group
+    assert rounds[0].tolist() == want_rounds.tolist() == [per_group] * 40
+    # bytes copied per round, summed over groups: the simulator's
     assert cnt[0][16:80].tolist() == want_bytes.tolist()
-    assert want_bytes[:64 // k].tolist() == [40 * 16 * k] * (64 // k)
+    if plain:       # and 16 k bytes per round per group
+        assert want_bytes[:64 // k].tolist() == [40 * 16 * k] * (64 // k)
 
 
 @pytest.mark.parametrize("waves", [1, 7])
 @pytest.mark.parametrize("kind", ["text", "csv"])
-def test_mrr_rounds_real_data(ctx, kind, waves):
+@pytest.mark.parametrize("plain", [True, False])
+def test_mrr_rounds_real_data(ctx, kind, waves, plain):
+    import paper_1606_00519_amd as gmp
     data = synth.slice_of(kind, 0, 4 << 20).tobytes()
     blocks = [oracle.compress_block(data[i:i + (1 << 20)], P()) for i in range(0, len(data), 1 << 20)]
     cnt = []
-    st, outs, rounds = decode_batch(ctx, blocks, flags=0, stats=True, waves=waves, counters=cnt)
+    st, outs, rounds = decode_batch(ctx, blocks, flags=gmp.FLAG_PLAIN_MRR if plain else 0, stats=True,
+                                    waves=waves, counters=cnt)
     assert np.all(st == 0)
     for b, o, r, c in zip(blocks, outs, rounds, cnt):
         rc, seqs, lits = oracle.block_tokens(b)
-        want, want_bytes = oracle.mrr_rounds(seqs, 64)
+        want, want_bytes = (oracle.mrr_rounds if plain else oracle.mrr_rounds_redirect)(seqs, 64)
         assert o == oracle.decompress_block(b)[1]
         assert not np.any(r & 0x80)   # no group was split
         assert r.tolist() == want.tolist()

@@ -340,6 +340,111 @@ def test_mrr_bounds_and_independent_groups(seed):
     assert oracle.mrr_rounds(far, 64)[0].tolist() == [1]
 
 
+# ----------------------------------------------------------------------------- MRR with redirected sources
+
+def _check_redirect_schedule(seqs, lits, G=64, jumps=2, span_limit=32768):
+    """The redirected schedule against facts outside the simulator: every
+    copy, read at its redirected distance, holds the bytes the sequential
+    decode puts there; every byte a copy reads is final before its round
+    (literals and earlier groups, or copies of earlier rounds); the rounds
+    never exceed the paper's rule's."""
+    seqs = np.asarray(seqs, np.int64)
+    rc, out = oracle.lz77_expand(seqs.astype(np.uint32), lits)
+    assert rc == 0
+    out = np.frombuffer(out, np.uint8)
+    rounds, bpr, sr, sd = oracle.mrr_rounds_redirect(seqs, G, jumps, span_limit, per_seq=True)
+    plain, _ = oracle.mrr_rounds(seqs, G)
+    assert np.all(rounds <= plain)
+    assert bpr.sum() == seqs[:, 1].sum()
+    L, M, D = seqs[:, 0], seqs[:, 1], seqs[:, 2]
+    dst = np.cumsum(L + M) - M
+    has = M > 0
+    assert np.all(sd[has] >= D[has])
+    moved = has & (sd != D)
+    assert np.all(D[moved] >= M[moved])                       # only copies that do not overlap themselves move
+    assert np.all((sr > 0) == has)
+    final = np.zeros(len(out), bool)
+    for g0 in range(0, len(seqs), G):
+        g1 = min(len(seqs), g0 + G)
+        g_start = int(dst[g0] - L[g0])
+        for i in range(g0, g1):                               # the group's literals
+            final[dst[i] - L[i]:dst[i]] = True
+        assert int(rounds[g0 // G]) == int(sr[g0:g1].max(initial=0))
+        for r in range(1, int(rounds[g0 // G]) + 1):
+            now = [i for i in range(g0, g1) if sr[i] == r]
+            for i in now:
+                d, m, p = int(sd[i]), int(M[i]), int(dst[i])
+                src = p - d
+                assert final[src:src + min(m, d)].all(), (i, r)
+                idx = src + np.arange(m) % d if d < m else src + np.arange(m)
+                assert np.array_equal(out[idx], out[p:p + m]), i
+            for i in now:
+                final[dst[i]:dst[i] + M[i]] = True
+        assert final[g_start:int(dst[g1 - 1] + M[g1 - 1])].all()
+
+
+def test_redirect_hand_example():
+    # "abcd", then three 4-byte copies at distance 4: each reads the previous
+    # one's output.  The paper's rule takes three rounds; one move sends the
+    # third copy to the first copy's source (two rounds), two moves send every
+    # copy to the literals (one round).
+    seqs = [[4, 4, 4], [0, 4, 4], [0, 4, 4]]
+    assert oracle.mrr_rounds(seqs, 64)[0].tolist() == [3]
+    assert oracle.mrr_rounds_redirect(seqs, 64, jumps=1)[0].tolist() == [2]
+    r, bpr, sr, sd = oracle.mrr_rounds_redirect(seqs, 64, jumps=2, per_seq=True)
+    assert r.tolist() == [1] and sr.tolist() == [1, 1, 1] and sd.tolist() == [4, 8, 12]
+    assert bpr[:2].tolist() == [12, 0]
+    # an overlapping copy (distance < length) is never moved, nor read through
+    seqs = [[4, 8, 2], [0, 4, 8]]
+    r, _, sr, sd = oracle.mrr_rounds_redirect(seqs, 64, per_seq=True)
+    assert sd.tolist() == [2, 8] and r.tolist() == [2]
+    # a copy reading past the end of the earlier destination stays where it is
+    seqs = [[8, 4, 8], [0, 4, 5]]
+    r, _, sr, sd = oracle.mrr_rounds_redirect(seqs, 64, per_seq=True)
+    assert sd.tolist() == [8, 5] and r.tolist() == [2]
+    _check_redirect_schedule([[4, 4, 4], [0, 4, 4], [0, 4, 4]], b"abcd")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_redirect_without_moves_is_the_paper_rule(seed):
+    seqs, _ = synth.random_tokens(900, seed, overlap_frac=0.3)
+    for G in (32, 64):
+        a = oracle.mrr_rounds(seqs, G)
+        for b in (oracle.mrr_rounds_redirect(seqs, G, jumps=0),
+                  oracle.mrr_rounds_redirect(seqs, G, jumps=2, span_limit=1)):   # no group is small enough
+            assert a[0].tolist() == b[0].tolist() and a[1].tolist() == b[1].tolist()
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("jumps", [1, 2, 3])
+def test_redirect_nesting_closed_form(k, jumps):
+    # chain element c of a group reads element c-1's output; after j moves it
+    # reads element c-1-j's, so ceil((64/k)/(j+1)) rounds per group
+    seqs, lits = synth.nesting_tokens(64 * 6, k, str_len=16)
+    r, bpr = oracle.mrr_rounds_redirect(seqs, 64, jumps=jumps)
+    want = -(-(64 // k) // (jumps + 1))
+    assert r.tolist() == [want] * 6
+    _check_redirect_schedule(seqs, lits, jumps=jumps)
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("overlap", [0.0, 0.3])
+def test_redirect_schedule_random(seed, overlap):
+    seqs, lits = synth.random_tokens(1500, seed, overlap_frac=overlap, window=2048)
+    _check_redirect_schedule(seqs, lits)
+
+
+@pytest.mark.parametrize("kind", ["text", "csv"])
+def test_redirect_schedule_real_data(kind):
+    data = synth.slice_of(kind, 0, 300_000).tobytes()
+    rc, seqs, lits = oracle.block_tokens(oracle.compress_block(data, P()))
+    assert rc == 0
+    _check_redirect_schedule(seqs, lits)
+    r, _ = oracle.mrr_rounds_redirect(seqs, 64)
+    plain, _ = oracle.mrr_rounds(seqs, 64)
+    assert r.sum() < plain.sum()
+
+
 # ----------------------------------------------------------------------------- corruption
 
 def _block(de=0, n=200_000):
