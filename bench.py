@@ -154,7 +154,7 @@ def cpu_baseline(streams: dict, size: int, threads: int, cpu_seconds: float) -> 
 def launch_shape(waves: int) -> str:
     if waves == 7:
         return ("one workgroup per block, 8 wavefronts: 7 decoders + fetcher (Huffman phase); "
-                "4 resolvers + fetcher + flusher (LZ77 phase)")
+                "6 resolvers + fetcher + flusher (LZ77 phase)")
     return f"one workgroup per block: {waves} decoder/resolver wavefront(s) + fetcher + flusher"
 
 

@@ -178,9 +178,11 @@ constexpr int kMaxLanes = 64 * kMaxDecWaves;
 // Workgroup shape.  kDec decoder wavefronts (they resolve in phase B) and a
 // fetcher, plus a flusher of its own for kDec in {1, 2, 4}.  At kDec = 7 the
 // workgroup has eight wavefronts, two per SIMD: phase A decodes on seven; in
-// phase B four resolve (one per SIMD: the copies on the resolution chain do
-// not share their SIMD with another resolver's preparation work), the
-// seventh decoder flushes and two rest.
+// phase B six resolve and the seventh decoder flushes.  With MRR's rounds
+// short (sources moved through the group's own copies), a resolver's
+// preparation of its next group (scans, literal copies, rounds) takes longer
+// than the resolution chain takes for the groups in between, so more
+// resolvers beat keeping the chain's copies alone on their SIMD.
 template <int kDec>
 constexpr uint32_t block_waves() {
   return kDec == 7 ? 8u : (uint32_t)kDec + 2u;
@@ -195,7 +197,7 @@ constexpr uint32_t flusher_wave() {
 }
 template <int kDec>
 constexpr int resolver_waves() {
-  return kDec == 7 ? 4 : kDec;  // wavefronts 0 .. resolver_waves() - 1
+  return kDec == 7 ? 6 : kDec;  // wavefronts 0 .. resolver_waves() - 1
 }
 // 16-byte rows of each decoder lane's bit ring: the largest power of two
 // the staging area holds for all lanes
@@ -1678,7 +1680,8 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
       // below g_out: it copies as soon as those it needs are final, possibly
       // before the groups in front of it have finished.
       const uint32_t need = min(readlane(wave_incl_max(has ? need_end : 0u), 63), g_out);
-      if (!wait_done(need)) break;
+      uint32_t seen_done = 0;
+      if (!wait_at_least(&s_misc.done_upto, need, seen_done, kSiteDone)) break;
       bool spilled = false;
       if (spill_mode) {
         // rounds past max_rounds, and copies whose source holds a byte that
@@ -1710,8 +1713,9 @@ __device__ void resolve_groups(const LzArgs& a, uint32_t w) {
           }
         }
       }
-      // its output is final once everything in front of it is
-      if (!wait_done(g_out)) break;
+      // its output is final once everything in front of it is (often seen
+      // by the wait above already)
+      if (seen_done < g_out && !wait_done(g_out)) break;
       if (spill_mode) spill_append(a, spilled, dst, D, M, lane);
       lds_release(&s_misc.done_upto, g_end);
       if (a.stats) {
