@@ -476,8 +476,9 @@ def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict
     of Nested back-references"): byte-level blocks of 1 MiB whose token
     streams hold k interleaved chains of 16-byte back-references, each copying
     the output of the one k sequences before it, so that every group of 64
-    sequences takes 64/k rounds of Multi-Round Resolution; Sequential Copying
-    of the same blocks beside it."""
+    sequences takes 64/k rounds of Multi-Round Resolution by the paper's rule
+    (ceil(64/k / 3) with sources moved through the group's own copies, the
+    default); Sequential Copying of the same blocks beside them."""
     import oracle
     import synth
     import paper_1606_00519_amd as gmp
@@ -499,7 +500,9 @@ def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict
         nb = max(1, (mib << 20) // raw)
         s = oracle.assemble_stream([blk] * nb, raw, raw * nb)
         data = want * nb
-        runs = {"mrr": (StreamRun(ctx, s, len(data)), gmp.MODE_MRR), "sc": (StreamRun(ctx, s, len(data)), gmp.MODE_SC)}
+        runs = {"mrr": (StreamRun(ctx, s, len(data)), gmp.MODE_MRR),
+                "mrr_plain": (StreamRun(ctx, s, len(data)), gmp.MODE_MRR | gmp.FLAG_PLAIN_MRR),
+                "sc": (StreamRun(ctx, s, len(data)), gmp.MODE_SC)}
         ms = time_modes(runs, max(3, steps // 2), warmup, waves)
         e = {"depth": 64 // k, "blocks": nb, "raw_bytes": len(data)}
         for m, (r, f) in runs.items():
@@ -511,6 +514,7 @@ def nesting_leg(ctx, steps: int, warmup: int, waves: int, mib: int = 64) -> dict
             r.close()
         res[f"depth{64 // k}"] = e
         log(f"nesting depth {64 // k}: MRR {e['mrr']['GBps']} GB/s ({e['mrr']['rounds_mean']} rounds), "
+            f"paper's rule {e['mrr_plain']['GBps']} GB/s ({e['mrr_plain']['rounds_mean']} rounds), "
             f"SC {e['sc']['GBps']} GB/s")
     return res
 
@@ -775,7 +779,7 @@ def main() -> int:
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--waves", type=int, default=7, choices=(1, 2, 4, 7),
                     help="decoder wavefronts per block (phase A); with 7, four of them resolve in phase B")
-    ap.add_argument("--legs", default="byte,compress,csv,nesting,multilaunch,batched,serve",
+    ap.add_argument("--legs", default="paper_rule,byte,compress,csv,nesting,multilaunch,batched,serve",
                     help="side legs beside the headline (comma-separated; '' = headline only)")
     ap.add_argument("--csv-mib", type=int, default=1024, help="size of the low-entropy CSV configuration")
     ap.add_argument("--batch-items", type=int, default=4096, help="batched form: items")
@@ -802,6 +806,13 @@ def main() -> int:
     modes = {m: mode_entry(size, comp[m], kernel_ms[m], stats[m], copy_ref["GBps"]) for m in ("mrr", "de")}
     log(f"headline: {value:.2f} GB/s (MRR {modes['mrr']['GBps']}, DE {modes['de']['GBps']})")
     side = {}
+    if "paper_rule" in legs:
+        # the headline MRR stream resolved by the paper's round rule alone
+        # (no source moved through the group's own copies): the rounds and
+        # bytes per round the paper's figures are about
+        side["paper_rule"] = side_leg(ctx, "paper-rule", data,
+                                      {"mrr": (streams["mrr"], gmp.MODE_MRR | gmp.FLAG_PLAIN_MRR)},
+                                      args.steps, args.warmup, args.waves, copy_ref["GBps"])
     if "byte" in legs:
         t0 = time.time()
         bs = {}
