@@ -270,6 +270,8 @@ __shared__ __attribute__((aligned(16))) uint32_t s_big[kRing / 4];     // lookup
 __shared__ __attribute__((aligned(16))) uint4 s_stage[kStageBytes / 16];  // bit rings, then staged tokens
 __shared__ Misc s_misc;
 __shared__ Seg s_seg;
+// exact restarts of the segmented decoder's second attempt (decode_segmented)
+__shared__ uint32_t s_xstart[kMaxLanes];
 
 __device__ __forceinline__ uint8_t* ring_ptr() { return reinterpret_cast<uint8_t*>(s_big); }
 __device__ __forceinline__ uint2* rec_ring() { return reinterpret_cast<uint2*>(s_stage); }
@@ -612,6 +614,7 @@ struct SegLane {
   GMEM uint8_t* lit_out;
   GMEM uint32_t* log;           // the first kLogN literal/length symbol boundaries from the entry
   uint32_t overlap;             // bits decoded without output before the segment, to get into step
+  uint32_t xstart;              // an exact symbol boundary to start at instead (kDone: none)
 };
 
 // The sub-block holding payload bit p, and the first bit a lane whose segment
@@ -689,8 +692,9 @@ __device__ void decode_segment(const SegLane& g, uint32_t L, uint32_t n_sub, uin
     nx = ring_word(rd);
     s_misc.rd[L] = rd - 4;
   };
-  uint32_t sb = sub_of(g.p_begin, n_sub);
-  uint32_t pos = warm_start(g.p_begin, sb, g.overlap);  // at most 3 words past base_word
+  uint32_t sb = sub_of(g.xstart != kDone ? g.xstart : g.p_begin, n_sub);
+  // at most 3 words past base_word
+  uint32_t pos = g.xstart != kDone ? g.xstart : warm_start(g.p_begin, sb, g.overlap);
   uint32_t sub_end = s_seg.sub_end[sb];
   uint32_t state = 0, n, kind, val;
   load(pos);
@@ -1905,7 +1909,7 @@ template <int kDec>
 __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, const GMEM uint8_t* payload_bytes,
                                  uint32_t n_sub, uint32_t n_seq, uint32_t n_lit, uint32_t payload, uint32_t lmax,
                                  uint32_t window, uint32_t max_match, GMEM uint64_t* ws_seq, GMEM uint8_t* ws_lit,
-                                 uint32_t overlap) {
+                                 uint32_t overlap, bool second) {
   constexpr uint32_t kThreads = block_threads<kDec>(), kLanes = 64 * kDec;
   Misc& sh = s_misc;
   const uint32_t t = threadIdx.x, wave = t >> 6;
@@ -1963,7 +1967,12 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
     // the lane's bit ring starts at the row of the first bit it decodes
     g.overlap = overlap;
-    g.base_word = (warm_start(g.p_begin, sub_of(g.p_begin, n_sub), overlap) / 32) & ~3u;
+    // a second attempt restarts a lane that fell out of step exactly where a
+    // lane in step before it ended (its first symbol boundary at or after
+    // this lane's segment start)
+    g.xstart = second && s_xstart[t] < g.p_end ? s_xstart[t] : kDone;
+    g.base_word = ((g.xstart != kDone ? g.xstart : warm_start(g.p_begin, sub_of(g.p_begin, n_sub), overlap)) / 32) &
+                  ~3u;
     // whole 16-byte rows: the fetcher moves rows, and the ring holds no partial one
     g.n_words = min(pw, (g.p_end / 32 + 8 + 3) & ~3u) - g.base_word;
     g.cap_rec = (uint32_t)cap_rec;
@@ -2039,7 +2048,24 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
   }
   __syncthreads();
   if (s_seg.bad) {
-    if (t == 0) sh.seg_reject = s_seg.bad;
+    if (t == 0) {
+      sh.seg_reject = s_seg.bad;
+      // Which lanes are on the true symbol path from their entry on: lane 0,
+      // lanes whose entry is a sub-block start, and lanes that met (or were
+      // repaired from) the exit of a lane on it.  A lane that failed or did
+      // not meet its predecessor restarts, in a second attempt, exactly at
+      // that predecessor's exit when the predecessor is on the path.
+      bool prev_on = false;
+      uint32_t prev_exit = kDone;
+      for (uint32_t k = 0; k < kLanes; k++) {
+        const uint32_t f = s_seg.flags[k];
+        const bool failed = (f & kSegFail) != 0;
+        const bool met = k == 0 ? s_seg.entry[0] == 0u : ((f & kSegRep) || s_seg.entry[k] == s_seg.exit_at[k - 1]);
+        s_xstart[k] = (failed || !met) && prev_on ? prev_exit : kDone;
+        prev_on = !failed && (!(f & kSegMid) || (met && prev_on));
+        prev_exit = s_seg.exit_at[k];
+      }
+    }
     return false;
   }
   // pack the effective streams into the final token stream
@@ -2326,16 +2352,19 @@ __device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t fla
   GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
   GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
   // Lanes that stayed out of step past what their repair covers (codes that
-  // fall into step slowly) get a second attempt with a far longer warm-up:
-  // it costs less than decoding every sub-block in one lane.
+  // fall into step slowly) get a second attempt: a lane that follows a lane
+  // on the true path restarts exactly at that lane's exit, the others warm up
+  // far longer.  It costs less than decoding every sub-block in one lane.
   bool segmented = false;
 #pragma nounroll
   for (uint32_t attempt = 0; attempt < 2; attempt++) {
     segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
-                                       max_match, ws_seq, ws_lit, attempt ? kOverlapRetry : kOverlapBits);
+                                       max_match, ws_seq, ws_lit, attempt ? kOverlapRetry : kOverlapBits,
+                                       attempt != 0);
     __syncthreads();  // the rejection reasons are in LDS for every thread
-    if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & (kRejIndex | kRejCode)) ||
-        sh.abort)
+    // (an invalid code with lanes that did not meet is most often a lane out
+    // of step; a corrupt block fails the second attempt too)
+    if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & kRejIndex) || sh.abort)
       break;
     if (t == 0) sh.seg_retry = 1;
   }

@@ -281,3 +281,24 @@ def test_slow_sync_blocks_decode_in_segments(ctx):
           f"rejections {[int(c[6]) for c in cnt]}", flush=True)
     assert all(c[0] == 1 for c in cnt)
     assert any(c[7] == 1 for c in cnt)
+
+
+def test_out_of_step_lanes_restart_exactly(ctx):
+    # In these 2 MiB CSV DE blocks a decoder lane stays out of step for more
+    # than 11 kbit, longer than its whole segment and than the second
+    # attempt's warm-up.  The second attempt restarts such a lane exactly at
+    # the exit of the lane before it (which is in step), so the block is
+    # still decoded in segments, not one lane per sub-block.
+    n = 2 << 20
+    blocks, raws = [], []
+    for b in (484, 491):
+        raw = synth.csv_rows(n, b * n).tobytes()
+        blocks.append(oracle.compress_block(raw, P(block_size=n, sub_target_raw=32768, de=1)))
+        raws.append(raw)
+    cnt = []
+    st, outs, _ = decode_batch(ctx, blocks, stats=True, waves=7, counters=cnt)
+    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, second attempts {[int(c[7]) for c in cnt]}, "
+          f"rejections {[int(c[6]) for c in cnt]}", flush=True)
+    assert np.all(st == 0) and outs == raws
+    assert all(c[0] == 1 for c in cnt)
+    assert all(c[7] == 1 for c in cnt)
