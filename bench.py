@@ -243,7 +243,7 @@ class StreamRun:
                 "bytes_per_round": [round(float(x) / max(groups, 1), 3) for x in rb[:last]],
                 "a2_paths": {"segmented": int(paths[1]), "per_sub_block": int(paths[2]), "byte_level": int(paths[3])},
                 "segmented_rejections": rej,
-                "segmented_second_attempts": int(c[:, self.gmp.STAT_SEG_RETRY].sum()),
+                "segmented_further_attempts": int(c[:, self.gmp.STAT_SEG_RETRY].sum()),
                 "repaired_lanes": int(c[:, self.gmp.STAT_REPAIRED].sum()),
                 "split_groups": int(c[:, self.gmp.STAT_SPLIT].sum())}
 

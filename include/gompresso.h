@@ -164,8 +164,9 @@ typedef struct {
                                    not meet, 16 last lane's end, 32 open literal run, 64 per-sub-block counts,
                                    128 repair failed; 0 when accepted or not attempted (after a second
                                    attempt: the second attempt's reasons) */
-#define GMP_STAT_SEG_RETRY 7    /* 1: segmented decoding was attempted a second time, with a longer warm-up
-                                   before each segment, because lanes stayed out of step */
+#define GMP_STAT_SEG_RETRY 7    /* further segmented attempts (0, 1 or 2) because lanes stayed out of step:
+                                   a lane after a lane on the true symbol path restarts exactly at that
+                                   lane's exit, the others warm up longer before their segment */
 #define GMP_STAT_SPILLED 8      /* back-references the decoding launch left to later launches
                                    (gmp_tuning.rounds_per_launch) */
 #define GMP_STAT_ROUND_BYTES 16 /* [16 + r]: back-reference bytes copied in round r + 1, over all groups

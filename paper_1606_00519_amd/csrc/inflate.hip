@@ -97,7 +97,8 @@ constexpr uint32_t kTightPolls = 64;          // polls of a hand-over counter be
 constexpr uint32_t kGRing = kRecRing / 64;    // staged group offsets
 constexpr uint32_t kSubMax = 512;             // most sub-blocks of a block decoded in segments
 constexpr uint32_t kOverlapBits = 768;        // bits a segment decoder reads ahead of its start to synchronise
-constexpr uint32_t kOverlapRetry = 8192;      // ... on a second attempt, when lanes stayed out of step
+constexpr uint32_t kOverlapRetry = 8192;      // ... on later attempts, when lanes stayed out of step
+constexpr uint32_t kSegAttempts = 3;          // segmented attempts before one lane per sub-block
 constexpr uint32_t kSnapBits = 2048;          // segment boundaries this close to a sub-block's end move past it
 constexpr bool kSegmentedDecode = true;
 constexpr uint32_t kDone = 0xFFFFFFFFu;       // progress value of a finished consumer
@@ -229,6 +230,7 @@ struct Misc {
   uint32_t rbytes[64];
   uint32_t n_split, n_de_rounds, a2_path, n_repaired, stall_site, seg_reject, seg_retry;
   uint32_t spill_n;  // back-references written to the block's spill list (groups append in order)
+  uint32_t seg_restarts;  // lanes a failed segmented attempt newly gave an exact restart
 };
 
 // State of the segmented Huffman decoder (A2 when the block qualifies).
@@ -2055,16 +2057,23 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
       // repaired from) the exit of a lane on it.  A lane that failed or did
       // not meet its predecessor restarts, in a second attempt, exactly at
       // that predecessor's exit when the predecessor is on the path.
+      // A restart found once stays: the exit of a lane on the path is the
+      // first true boundary at or after the next lane's segment start.
       bool prev_on = false;
-      uint32_t prev_exit = kDone;
+      uint32_t prev_exit = kDone, added = 0;
       for (uint32_t k = 0; k < kLanes; k++) {
         const uint32_t f = s_seg.flags[k];
         const bool failed = (f & kSegFail) != 0;
         const bool met = k == 0 ? s_seg.entry[0] == 0u : ((f & kSegRep) || s_seg.entry[k] == s_seg.exit_at[k - 1]);
-        s_xstart[k] = (failed || !met) && prev_on ? prev_exit : kDone;
-        prev_on = !failed && (!(f & kSegMid) || (met && prev_on));
+        const bool exact = second && s_xstart[k] != kDone;
+        if (!exact && (failed || !met) && prev_on) {
+          s_xstart[k] = prev_exit;
+          added++;
+        }
+        prev_on = !failed && (!(f & kSegMid) || exact || (met && prev_on));
         prev_exit = s_seg.exit_at[k];
       }
+      sh.seg_restarts = added;
     }
     return false;
   }
@@ -2356,17 +2365,19 @@ __device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t fla
   // on the true path restarts exactly at that lane's exit, the others warm up
   // far longer.  It costs less than decoding every sub-block in one lane.
   bool segmented = false;
+  for (uint32_t k = t; k < kMaxLanes; k += block_threads<kDec>()) s_xstart[k] = kDone;
 #pragma nounroll
-  for (uint32_t attempt = 0; attempt < 2; attempt++) {
+  for (uint32_t attempt = 0; attempt < kSegAttempts; attempt++) {
     segmented = decode_segmented<kDec>(job, idx, payload_bytes, n_sub, n_seq, n_lit, payload, lmax, window,
                                        max_match, ws_seq, ws_lit, attempt ? kOverlapRetry : kOverlapBits,
                                        attempt != 0);
     __syncthreads();  // the rejection reasons are in LDS for every thread
     // (an invalid code with lanes that did not meet is most often a lane out
     // of step; a corrupt block fails the second attempt too)
-    if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & kRejIndex) || sh.abort)
+    if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & kRejIndex) || sh.abort ||
+        (attempt > 0 && sh.seg_restarts == 0))
       break;
-    if (t == 0) sh.seg_retry = 1;
+    if (t == 0 && attempt + 1 < kSegAttempts) sh.seg_retry = attempt + 1;
   }
   uint32_t carry[4] = {0, 0, 0, 0};
   for (uint32_t c = 0; !segmented && c < n_sub; c += kLanes) {
@@ -2472,6 +2483,7 @@ __device__ int inflate_block(const DevJob& job, uint32_t flags) {
     sh.stall_site = 0;
     sh.seg_reject = 0;
     sh.seg_retry = 0;
+    sh.seg_restarts = 0;
     sh.spill_n = 0;
   }
   if (t < 64) sh.rbytes[t] = 0;

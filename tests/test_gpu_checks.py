@@ -277,10 +277,10 @@ def test_slow_sync_blocks_decode_in_segments(ctx):
     cnt = []
     st, outs, _ = decode_batch(ctx, blocks, stats=True, waves=7, counters=cnt)
     assert np.all(st == 0) and outs == raws
-    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, second attempts {[int(c[7]) for c in cnt]}, "
+    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, further attempts {[int(c[7]) for c in cnt]}, "
           f"rejections {[int(c[6]) for c in cnt]}", flush=True)
     assert all(c[0] == 1 for c in cnt)
-    assert any(c[7] == 1 for c in cnt)
+    assert any(c[7] >= 1 for c in cnt)
 
 
 def test_out_of_step_lanes_restart_exactly(ctx):
@@ -297,8 +297,27 @@ def test_out_of_step_lanes_restart_exactly(ctx):
         raws.append(raw)
     cnt = []
     st, outs, _ = decode_batch(ctx, blocks, stats=True, waves=7, counters=cnt)
-    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, second attempts {[int(c[7]) for c in cnt]}, "
+    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, further attempts {[int(c[7]) for c in cnt]}, "
           f"rejections {[int(c[6]) for c in cnt]}", flush=True)
     assert np.all(st == 0) and outs == raws
     assert all(c[0] == 1 for c in cnt)
-    assert all(c[7] == 1 for c in cnt)
+    assert all(c[7] >= 1 for c in cnt)
+
+
+def test_runs_of_slow_lanes_restart_in_turn(ctx):
+    # Here two neighbouring lanes at a block's start both stay out of step for
+    # longer than a segment (the second for more than 12 kbit): the second
+    # attempt restarts the first exactly, the third restarts the second at the
+    # first's new exit.
+    n = 2 << 20
+    blocks, raws = [], []
+    for b in (167, 255):
+        raw = synth.csv_rows(n, b * n).tobytes()
+        blocks.append(oracle.compress_block(raw, P(block_size=n, sub_target_raw=32768, de=1)))
+        raws.append(raw)
+    cnt = []
+    st, outs, _ = decode_batch(ctx, blocks, stats=True, waves=7, counters=cnt)
+    print(f"[gpu] paths {[int(c[0]) for c in cnt]}, further attempts {[int(c[7]) for c in cnt]}, "
+          f"rejections {[int(c[6]) for c in cnt]}", flush=True)
+    assert np.all(st == 0) and outs == raws
+    assert all(c[0] == 1 for c in cnt)
