@@ -324,7 +324,7 @@ typedef struct {
   uint8_t* d_out;       /* device, 16-byte aligned: the compressed block */
   uint64_t out_cap;     /* at least gmp_compress_bound(in_len) */
   uint64_t* d_out_len;  /* device: receives the compressed block's size */
-  int32_t* d_status;    /* device: GMP_OK, or GMP_ESTALL if a bounded wait ran out */
+  int32_t* d_status;    /* device: GMP_OK once the block is written */
 } gmp_compress_job;
 #define GMP_COMPRESS_MAX_BLOCK (64u << 20)
 /* Largest compressed size of a block of in_len bytes. */

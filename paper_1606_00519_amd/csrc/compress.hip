@@ -12,15 +12,18 @@
 //      window before their eighth, so every position sees up to the window's
 //      history): every position gets the most recent earlier position with
 //      its key's hash, its candidate (the candidates form hash chains);
-//   L  every thread takes positions and measures the match at each candidate
-//      of the chain (up to kChain of them, within the window) and at
-//      distances 1-4, keeping the longest (the nearest on a tie);
-//   P  one wavefront parses greedily from the block's start: a literal run
-//      ends at the first position whose match (truncated under the DE rule)
-//      is at least 3 bytes long, found 64 positions at a time with a ballot;
-//      a run that reaches 255 bytes becomes a sequence of its own.  Another
-//      wavefront streams the per-position matches into an LDS ring ahead of
-//      it;
+//   L  the workgroup takes 512 positions at a time; each thread walks its
+//      position's chain (up to kChain candidates within the window) in an
+//      LDS ring of the candidates' links, then loads the eight bytes at every
+//      candidate and at distances 1-4 at once and keeps the longest match
+//      (the first of equals);
+//   P  each wavefront parses one eighth of the block greedily (a block
+//      under 64 KiB: wavefront 0 all of it): a literal run ends at the first
+//      position whose match (cut at the part's end, and under the DE rule) is
+//      at least 3 bytes long, found 64 positions at a time with a ballot; a
+//      run that reaches 255 bytes becomes a sequence of its own.  Under DE a
+//      part's records are padded with empty ones to a multiple of 64, so the
+//      next part starts a group.  The parts' records are then put in order;
 //   A  the whole workgroup writes the literal bytes after the records, from
 //      prefix sums over the records, then the header and zero padding.
 //
@@ -39,18 +42,13 @@ constexpr uint32_t kWaves = 8, kThreads = 64 * kWaves;
 constexpr uint32_t kHashBits = 12, kHashSize = 1u << kHashBits;  // per walker
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kChain = 8;                  // candidates measured per position
-constexpr uint32_t kRingEnt = 16384;            // staged per-position matches (64 KiB)
-constexpr uint32_t kStageEnt = 256;             // entries per staging copy (1 KiB)
+constexpr uint32_t kSegMin = 65536;             // blocks at least this long are parsed in kWaves parts
 constexpr uint32_t kMagicByte = 0x59504D47u;    // 'GMPY'
-constexpr uint64_t kSpinTicks = 100000000ull;   // about one second of the 100 MHz clock
-constexpr int kOK = 0, kESTALL = -12;
+constexpr int kOK = 0;
 
 __shared__ __attribute__((aligned(16))) uint32_t s_lds[kWaves * kHashSize];  // hash tables, then the match ring
 struct CMisc {
-  uint32_t staged;      // stager -> parser: entries of best[] present in the ring (absolute position)
-  uint32_t consumed;    // parser -> stager: positions below this are no longer read
-  uint32_t n_seq, n_lit;
-  uint32_t abort;
+  uint32_t seg_seq[kWaves], seg_lit[kWaves];  // records and literal bytes of each part's parse
   uint32_t wave_sum[2][kWaves];
 };
 __shared__ CMisc s_cm;
@@ -59,28 +57,6 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
-__device__ __forceinline__ uint32_t lds_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// a bounded wait: false once it has lasted about a second (or the block gave up)
-struct Spin {
-  uint64_t t0 = 0;
-  __device__ bool pause() {
-    if (__hip_atomic_load(&s_cm.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
-    const uint64_t now = (uint64_t)wall_clock64();
-    if (t0 == 0) t0 = now;
-    else if (now - t0 > kSpinTicks) {
-      __hip_atomic_store(&s_cm.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(1);
-    return true;
-  }
-};
-
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
@@ -116,7 +92,14 @@ __device__ void block_excl_scan2(uint32_t& a, uint32_t& b, uint32_t& tot_a, uint
   __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t key3(const GMEM uint8_t* in, uint32_t p) {
+// Loads of 4 and 8 bytes at any byte address (the target reads global
+// memory unaligned).
+typedef uint32_t __attribute__((aligned(1))) u32u;
+typedef uint64_t __attribute__((aligned(1))) u64u;
+
+// the 3-byte key at p (p + 3 <= n)
+__device__ __forceinline__ uint32_t key3(const GMEM uint8_t* in, uint32_t p, uint32_t n) {
+  if (p + 4 <= n) return *(const GMEM u32u*)(in + p) & 0xFFFFFFu;
   return (uint32_t)in[p] | ((uint32_t)in[p + 1] << 8) | ((uint32_t)in[p + 2] << 16);
 }
 __device__ __forceinline__ uint32_t hash_key(uint32_t k) { return (k * 2654435761u) >> (32 - kHashBits); }
@@ -134,7 +117,7 @@ __device__ void walk(const GMEM uint8_t* in, uint32_t n, uint32_t window, GMEM u
   for (uint32_t c = start; c < hi; c += 64) {
     const uint32_t p = c + lane;
     const bool has = p + 3 <= n;
-    const uint32_t h = has ? hash_key(key3(in, p)) : 0u;
+    const uint32_t h = has ? hash_key(key3(in, p, n)) : 0u;
     const uint32_t b = has ? table[h] : 0u;
     __builtin_amdgcn_wave_barrier();
     if (has) atomicMax(&table[h], p + 1);  // the most recent position of the 64 holds the bucket
@@ -143,149 +126,179 @@ __device__ void walk(const GMEM uint8_t* in, uint32_t n, uint32_t window, GMEM u
 }
 
 // ---------------------------------------------------------------- L
-__device__ __forceinline__ uint32_t match_len(const GMEM uint8_t* in, uint32_t p, uint32_t s, uint32_t cap) {
-  uint32_t L = 0;
+// Candidates' links, for the chain walks of L, live in an LDS ring of the
+// last kRingC positions (the hash tables' space): the workgroup measures
+// kThreads positions at a time, so a chain reaches kRingC - kThreads
+// positions back at most.
+constexpr uint32_t kRingC = kWaves * kHashSize;
+constexpr uint32_t kReach = kRingC - kThreads;
+
+// The rest of a match whose first eight bytes agree (p + cap <= n).
+__device__ __noinline__ uint32_t match_rest(const GMEM uint8_t* in, uint32_t p, uint32_t s, uint32_t cap) {
+  uint32_t L = 8;
+  for (; L + 8 <= cap; L += 8) {
+    const uint64_t x = *(const GMEM u64u*)(in + s + L) ^ *(const GMEM u64u*)(in + p + L);
+    if (x) return L + ((uint32_t)__builtin_ctzll(x) >> 3);
+  }
   while (L < cap && in[s + L] == in[p + L]) L++;
   return L;
 }
-// best[p] = length | distance << 9 (0 when no match of 3 bytes or more)
-__device__ void measure(const GMEM uint8_t* in, uint32_t n, uint32_t window, uint32_t max_match,
-                        const GMEM uint32_t* cand, GMEM uint32_t* best) {
-  for (uint32_t p = threadIdx.x; p < n; p += kThreads) {
-    uint32_t bl = 0, bd = 0;
-    if (p + 3 <= n) {
-      const uint32_t cap = min(max_match, n - p);
-      // short distances first (runs and short periods), then the hash chain
-      for (uint32_t d = 1; d <= 4 && d <= p && d <= window; d++) {
-        if (bl >= cap) break;
-        const uint32_t L = match_len(in, p, p - d, cap);
-        if (L > bl) {
-          bl = L;
-          bd = d;
-        }
-      }
-      uint32_t c = cand[p];
-      for (uint32_t k = 0; k < kChain && c != kNone && c < p && p - c <= window && bl < cap; k++) {
-        if (p - c > 4) {
-          const uint32_t L = match_len(in, p, c, cap);
-          if (L > bl) {
-            bl = L;
-            bd = p - c;
-          }
-        }
-        c = cand[c];
+
+// The best match at p: length | distance << 9 (0 when none of 3 bytes or
+// more).  Distances 1-4 first (runs and short periods), then up to kChain
+// candidates of the hash chain; the longest wins, the first of equals.  The
+// chain is walked in LDS first; then the eight bytes at every candidate are
+// loaded at once, so the loads overlap.
+__device__ __forceinline__ uint32_t best_match(const GMEM uint8_t* in, uint32_t n, uint32_t window,
+                                               uint32_t max_match, uint32_t p) {
+  if (p + 3 > n) return 0u;
+  const uint32_t cap = min(max_match, n - p);
+  const uint32_t reach = min(window, kReach);
+  uint32_t cs[4 + kChain];
+  bool ok[4 + kChain];
+#pragma unroll
+  for (uint32_t d = 1; d <= 4; d++) {
+    ok[d - 1] = d <= p && d <= window;
+    cs[d - 1] = ok[d - 1] ? p - d : p;
+  }
+  uint32_t c = s_lds[p % kRingC];
+  bool live = true;
+#pragma unroll
+  for (uint32_t k = 0; k < kChain; k++) {
+    live = live && c != kNone && c < p && p - c <= reach;
+    ok[4 + k] = live && p - c > 4;
+    cs[4 + k] = ok[4 + k] ? c : p;
+    c = live ? s_lds[c % kRingC] : kNone;
+  }
+  uint32_t bl = 0, bd = 0;
+  if (cap >= 8) {
+    const uint64_t head = *(const GMEM u64u*)(in + p);
+    uint64_t v[4 + kChain];
+#pragma unroll
+    for (uint32_t k = 0; k < 4 + kChain; k++) v[k] = *(const GMEM u64u*)(in + cs[k]);
+#pragma unroll
+    for (uint32_t k = 0; k < 4 + kChain; k++) {
+      if (!ok[k] || bl >= cap) continue;
+      const uint64_t x = v[k] ^ head;
+      const uint32_t L = x ? (uint32_t)__builtin_ctzll(x) >> 3 : match_rest(in, p, cs[k], cap);
+      if (L > bl) {
+        bl = L;
+        bd = p - cs[k];
       }
     }
-    best[p] = bl >= 3 ? (bl | (bd << 9)) : 0u;
+  } else {
+    for (uint32_t k = 0; k < 4 + kChain; k++) {
+      if (!ok[k] || bl >= cap) continue;
+      uint32_t L = 0;
+      while (L < cap && in[cs[k] + L] == in[p + L]) L++;
+      if (L > bl) {
+        bl = L;
+        bd = p - cs[k];
+      }
+    }
+  }
+  return bl >= 3 ? (bl | (bd << 9)) : 0u;
+}
+// best[p] for every position, kThreads positions at a time: the ring first
+// takes their candidates (every thread, after the previous positions' walks
+// are done), then each thread measures its position.
+__device__ void measure(const GMEM uint8_t* in, uint32_t n, uint32_t window, uint32_t max_match,
+                        const GMEM uint32_t* cand, GMEM uint32_t* best) {
+  const uint32_t t = threadIdx.x;
+  for (uint32_t P = 0; P < n; P += kThreads) {
+    const uint32_t p = P + t;
+    __syncthreads();
+    if (p < n) s_lds[p % kRingC] = cand[p];
+    __syncthreads();
+    if (p < n) best[p] = best_match(in, n, window, max_match, p);
   }
 }
 
 // ---------------------------------------------------------------- P
-// The stager wavefront keeps best[] entries [consumed, consumed + kRingEnt)
-// in the LDS ring, 1 KiB per copy.
-__device__ void stage_matches(const GMEM uint32_t* best, uint32_t n) {
+// The greedy parse of positions [lo, hi) by one wavefront, from best[]: a
+// literal run ends at the first position whose match (cut to end at hi, and
+// under the DE rule) is at least 3 bytes long; a run that reaches 255 bytes
+// becomes a sequence of its own.  DE: every match of a group of 64 sequences
+// must end at or before the group's high-water mark, which is the cursor
+// while the group has no back-reference yet, then the destination of its
+// first one (a match is cut to end there; under 3 bytes it is no match).
+// The records go to rec[0 ..); with pad the count is rounded up to a
+// multiple of 64 with empty records, so that the next part starts a group.
+__device__ void parse(const GMEM uint32_t* best, uint32_t lo, uint32_t hi, uint32_t de, bool pad,
+                      GMEM uint32_t* rec, uint32_t& n_seq_out, uint32_t& n_lit_out) {
   const uint32_t lane = lane_id();
-  uint32_t staged = 0;
-  Spin sp;
-  while (staged < n) {
-    const uint32_t cons = lds_acquire(&s_cm.consumed);
-    if (cons == kNone) return;  // the parser has finished
-    // up to four copies of 256 entries: lane l moves entries 4l..4l+3 of
-    // each (16 bytes; best[] is padded to 256 entries); loads first
-    uint32_t k = 0;
-    uint4 v[4];
-#pragma unroll
-    for (uint32_t j = 0; j < 4; j++) {
-      const uint32_t s0 = staged + j * kStageEnt;
-      if (k == j && s0 < n && s0 + kStageEnt <= cons + kRingEnt) {
-        const GMEM uint32_t* q = best + s0 + 4 * lane;
-        v[j] = make_uint4(q[0], q[1], q[2], q[3]);
-        k++;
-      }
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < 4; j++)
-      if (j < k) *(uint4*)&s_lds[(staged + j * kStageEnt + 4 * lane) % kRingEnt] = v[j];
-    staged += k * kStageEnt;
-    const bool issued = k > 0;
-    if (issued) {
-      __builtin_amdgcn_s_waitcnt(0);
-      lds_release(&s_cm.staged, min(staged, n));
-      sp = Spin();
-    } else if (!sp.pause()) {
-      return;
-    }
-  }
-}
-
-struct ParseOut {
-  GMEM uint32_t* rec;  // records, one u32 each
-  uint32_t n_seq, n_lit;
-};
-
-// The greedy parse (wavefront 0).  DE: every match of a group of 64
-// sequences must end at or before the group's high-water mark, which is the
-// cursor while the group has no back-reference yet, then the destination of
-// its first one (a match is cut to end there; under 3 bytes it is no match).
-__device__ bool parse(uint32_t n, uint32_t de, GMEM uint32_t* rec, uint32_t& n_seq_out, uint32_t& n_lit_out) {
-  const uint32_t lane = lane_id();
-  uint32_t pos = 0, lit_start = 0, n_seq = 0, n_lit = 0, hwm = 0, staged = 0;
+  uint32_t pos = lo, lit_start = lo, n_seq = 0, n_lit = 0, hwm = 0;
   bool frozen = false;
-  Spin sp;
+  // records collect one per lane and leave 64 at a time (256 bytes)
+  uint32_t rbuf = 0;
   auto emit = [&](uint32_t lit, uint32_t m, uint32_t d) {
-    if (lane == 0) rec[n_seq] = lit | ((m ? m - 3 : 0u) << 8) | (d << 16);
+    const uint32_t r = lit | ((m ? m - 3 : 0u) << 8) | (d << 16);
+    rbuf = lane == (n_seq & 63u) ? r : rbuf;
+    if ((n_seq & 63u) == 63u) rec[n_seq - 63 + lane] = rbuf;
     n_seq++;
     n_lit += lit;
     if (n_seq % 64 == 0) frozen = false;
   };
-  while (pos < n) {
+  while (pos < hi) {
     // the positions this step looks at: up to 64, not past the point where
-    // the literal run reaches 255 bytes (a sequence of its own)
-    const uint32_t end = min(min(pos + 64, n), lit_start + 255);
-    while (staged < end) {
-      staged = lds_acquire(&s_cm.staged);
-      if (staged >= end) break;
-      if (!sp.pause()) return false;
-    }
-    sp = Spin();
+    // the literal run reaches 255 bytes
+    const uint32_t end = min(min(pos + 64, hi), lit_start + 255);
     const uint32_t q = pos + lane;
-    uint32_t cap = 0, d = 0;
+    uint32_t L = 0, d = 0;
     if (q < end) {
-      const uint32_t b = s_lds[q % kRingEnt];
-      const uint32_t L = b & 511u;
+      const uint32_t b = best[q];
+      L = min(b & 511u, hi - q);
       d = b >> 9;
+    }
+    // every sequence whose match starts in [pos, end), from these 64 entries:
+    // the next match is the first position at or after the cursor whose
+    // match is at least 3 bytes long.  The lanes that hold such a match are
+    // one mask, worked out again only when the DE state changes (a group's
+    // first match, a group's end).
+    uint32_t cap = 0;
+    auto matches = [&]() -> uint64_t {
       cap = L;
       if (de && L) {
         const uint32_t lim = frozen ? hwm : q;  // the cursor would be at q
         const uint32_t src = q - d;
         cap = lim > src ? min(L, lim - src) : 0u;
       }
-    }
-    const uint64_t ok = __ballot(cap >= 3);
-    if (!ok) {
-      pos = end;
-      if (pos - lit_start == 255) {
-        emit(255, 0, 0);
-        lit_start = pos;
+      return __ballot(cap >= 3);
+    };
+    uint64_t ok = matches();
+    uint32_t cur = pos;
+    for (;;) {
+      const uint64_t from = ok & (~0ull << (cur - pos));  // cur - pos < 64 here
+      if (!from) {
+        cur = end;
+        break;
       }
-      lds_release(&s_cm.consumed, pos);
-      continue;
+      const uint32_t f = (uint32_t)__builtin_ctzll(from);
+      const uint32_t qm = pos + f, m = readlane(cap, f), dm = readlane(d, f);
+      bool changed = false;
+      if (de && !frozen) {
+        frozen = true;
+        hwm = qm;
+        changed = true;
+      }
+      emit(qm - lit_start, m, dm);
+      changed = changed || (de && !frozen);
+      cur = qm + m;
+      lit_start = cur;
+      if (cur >= end) break;
+      if (changed) ok = matches();
     }
-    const uint32_t f = (uint32_t)__builtin_ctzll(ok);
-    const uint32_t qm = pos + f, m = readlane(cap, f), dm = readlane(d, f);
-    if (de && !frozen) {
-      frozen = true;
-      hwm = qm;
+    pos = cur;
+    if (pos - lit_start == 255) {
+      emit(255, 0, 0);
+      lit_start = pos;
     }
-    emit(qm - lit_start, m, dm);
-    pos = qm + m;
-    lit_start = pos;
-    lds_release(&s_cm.consumed, pos);
   }
   if (pos > lit_start) emit(pos - lit_start, 0, 0);
+  while (pad && (n_seq & 63u)) emit(0, 0, 0);
+  if (lane < (n_seq & 63u)) rec[(n_seq & ~63u) + lane] = rbuf;
   n_seq_out = n_seq;
   n_lit_out = n_lit;
-  return true;
 }
 
 // ---------------------------------------------------------------- kernel
@@ -299,13 +312,6 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   GMEM uint32_t* cand = (GMEM uint32_t*)job.ws;
   GMEM uint32_t* best = cand + ((job.in_len + 255) & ~255ull);
   const uint32_t n = (uint32_t)job.in_len;
-  if (t == 0) {
-    s_cm.staged = 0;
-    s_cm.consumed = 0;
-    s_cm.abort = 0;
-    s_cm.n_seq = 0;
-    s_cm.n_lit = 0;
-  }
   __syncthreads();
   // W
   walk(in, n, prm.window, cand, wave);
@@ -316,32 +322,35 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   for (uint32_t p = n + t; p < ((n + 255) & ~255u); p += kThreads) best[p] = 0;  // staging reads whole KiBs
   __threadfence();
   __syncthreads();
-  // P
+  // P: a block of at least kSegMin bytes is parsed in kWaves parts at once
+  // (one per wavefront, into the candidate area, free after L; a match does
+  // not cross a part's end), a shorter one by wavefront 0 alone; then the
+  // parts' records go to the output, in order
   GMEM uint32_t* rec = (GMEM uint32_t*)(out + 32);
-  bool ok = true;
-  if (wave == 0) {
+  const uint32_t parts = n >= kSegMin ? kWaves : 1u;
+  const uint32_t part = parts == 1 ? n : ((n + kWaves - 1) / kWaves + 63) & ~63u;
+  const uint32_t lo = wave < parts ? min(n, wave * part) : n, hi = wave < parts ? min(n, lo + part) : n;
+  {
     uint32_t ns = 0, nl = 0;
-    ok = parse(n, prm.de, rec, ns, nl);
+    parse(best, lo, hi, prm.de, prm.de && wave + 1 < parts, cand + lo, ns, nl);
     if (lane == 0) {
-      s_cm.n_seq = ns;
-      s_cm.n_lit = nl;
-      if (!ok) s_cm.abort = 1;
+      s_cm.seg_seq[wave] = ns;
+      s_cm.seg_lit[wave] = nl;
     }
-    lds_release(&s_cm.consumed, kNone);
-  } else if (wave == 1) {
-    stage_matches(best, n);
   }
   __threadfence();
   __syncthreads();
-  if (s_cm.abort) {
-    if (t == 0) {
-      *job.status = kESTALL;
-      *job.out_len = 0;
-    }
-    return;
+  uint32_t n_seq = 0, n_lit = 0;
+  for (uint32_t w = 0; w < kWaves; w++) {
+    const uint32_t ns = s_cm.seg_seq[w];
+    const GMEM uint32_t* src = cand + (w < parts ? min(n, w * part) : n);
+    for (uint32_t i = t; i < ns; i += kThreads) rec[n_seq + i] = src[i];
+    n_seq += ns;
+    n_lit += s_cm.seg_lit[w];
   }
+  __threadfence();
+  __syncthreads();
   // A: literals after the records; the records' positions from prefix sums
-  const uint32_t n_seq = s_cm.n_seq, n_lit = s_cm.n_lit;
   const uint64_t rec_bytes = (4ull * n_seq + 15) & ~15ull;
   GMEM uint8_t* lit_out = out + 32 + rec_bytes;
   uint32_t carry_pos = 0, carry_lit = 0;
