@@ -128,10 +128,13 @@ __device__ void walk(const GMEM uint8_t* in, uint32_t n, uint32_t window, GMEM u
 // ---------------------------------------------------------------- L
 // Candidates' links, for the chain walks of L, live in an LDS ring of the
 // last kRingC positions (the hash tables' space): the workgroup measures
-// kThreads positions at a time, so a chain reaches kRingC - kThreads
-// positions back at most.
+// kStep positions at a time (kPer per thread), so a chain reaches
+// kRingC - kStep positions back at most.
+constexpr uint32_t kPer = 1;
+constexpr uint32_t kStep = kPer * kThreads;
 constexpr uint32_t kRingC = kWaves * kHashSize;
-constexpr uint32_t kReach = kRingC - kThreads;
+constexpr uint32_t kReach = kRingC - kStep;
+constexpr uint32_t kCand = 4 + kChain;  // distances 1-4, then the chain
 
 // The rest of a match whose first eight bytes agree (p + cap <= n).
 __device__ __noinline__ uint32_t match_rest(const GMEM uint8_t* in, uint32_t p, uint32_t s, uint32_t cap) {
@@ -144,73 +147,88 @@ __device__ __noinline__ uint32_t match_rest(const GMEM uint8_t* in, uint32_t p, 
   return L;
 }
 
-// The best match at p: length | distance << 9 (0 when none of 3 bytes or
-// more).  Distances 1-4 first (runs and short periods), then up to kChain
-// candidates of the hash chain; the longest wins, the first of equals.  The
-// chain is walked in LDS first; then the eight bytes at every candidate are
-// loaded at once, so the loads overlap.
-__device__ __forceinline__ uint32_t best_match(const GMEM uint8_t* in, uint32_t n, uint32_t window,
-                                               uint32_t max_match, uint32_t p) {
-  if (p + 3 > n) return 0u;
-  const uint32_t cap = min(max_match, n - p);
+// The best matches at kPer positions: length | distance << 9 (0 when none of
+// 3 bytes or more).  Distances 1-4 first (runs and short periods), then up to
+// kChain candidates of the hash chain; the longest wins, the first of
+// equals.  The chains are walked in LDS first; then the eight bytes at every
+// candidate of every position are loaded at once, so the loads overlap.
+__device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n, uint32_t window,
+                                             uint32_t max_match, const uint32_t (&p)[kPer],
+                                             uint32_t (&res)[kPer]) {
   const uint32_t reach = min(window, kReach);
-  uint32_t cs[4 + kChain];
-  bool ok[4 + kChain];
+  uint32_t cs[kPer][kCand], cap[kPer];
+  bool ok[kPer][kCand], live[kPer];
+  uint32_t c[kPer];
 #pragma unroll
-  for (uint32_t d = 1; d <= 4; d++) {
-    ok[d - 1] = d <= p && d <= window;
-    cs[d - 1] = ok[d - 1] ? p - d : p;
+  for (uint32_t i = 0; i < kPer; i++) {
+    const bool has = p[i] + 3 <= n;
+    cap[i] = has ? min(max_match, n - p[i]) : 0u;
+#pragma unroll
+    for (uint32_t d = 1; d <= 4; d++) {
+      ok[i][d - 1] = has && d <= p[i] && d <= window;
+      cs[i][d - 1] = ok[i][d - 1] ? p[i] - d : p[i];
+    }
+    c[i] = has ? s_lds[p[i] % kRingC] : kNone;
+    live[i] = has;
   }
-  uint32_t c = s_lds[p % kRingC];
-  bool live = true;
 #pragma unroll
   for (uint32_t k = 0; k < kChain; k++) {
-    live = live && c != kNone && c < p && p - c <= reach;
-    ok[4 + k] = live && p - c > 4;
-    cs[4 + k] = ok[4 + k] ? c : p;
-    c = live ? s_lds[c % kRingC] : kNone;
-  }
-  uint32_t bl = 0, bd = 0;
-  if (cap >= 8) {
-    const uint64_t head = *(const GMEM u64u*)(in + p);
-    uint64_t v[4 + kChain];
 #pragma unroll
-    for (uint32_t k = 0; k < 4 + kChain; k++) v[k] = *(const GMEM u64u*)(in + cs[k]);
-#pragma unroll
-    for (uint32_t k = 0; k < 4 + kChain; k++) {
-      if (!ok[k] || bl >= cap) continue;
-      const uint64_t x = v[k] ^ head;
-      const uint32_t L = x ? (uint32_t)__builtin_ctzll(x) >> 3 : match_rest(in, p, cs[k], cap);
-      if (L > bl) {
-        bl = L;
-        bd = p - cs[k];
-      }
-    }
-  } else {
-    for (uint32_t k = 0; k < 4 + kChain; k++) {
-      if (!ok[k] || bl >= cap) continue;
-      uint32_t L = 0;
-      while (L < cap && in[cs[k] + L] == in[p + L]) L++;
-      if (L > bl) {
-        bl = L;
-        bd = p - cs[k];
-      }
+    for (uint32_t i = 0; i < kPer; i++) {
+      live[i] = live[i] && c[i] != kNone && c[i] < p[i] && p[i] - c[i] <= reach;
+      ok[i][4 + k] = live[i] && p[i] - c[i] > 4;
+      cs[i][4 + k] = ok[i][4 + k] ? c[i] : p[i];
+      c[i] = live[i] ? s_lds[c[i] % kRingC] : kNone;
     }
   }
-  return bl >= 3 ? (bl | (bd << 9)) : 0u;
+  uint64_t head[kPer], v[kPer][kCand];
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++) {
+    const bool wide = cap[i] >= 8;  // then every candidate's eight bytes lie inside the block
+    head[i] = wide ? *(const GMEM u64u*)(in + p[i]) : 0ull;
+#pragma unroll
+    for (uint32_t k = 0; k < kCand; k++) v[i][k] = wide ? *(const GMEM u64u*)(in + cs[i][k]) : 0ull;
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++) {
+    uint32_t bl = 0, bd = 0;
+    for (uint32_t k = 0; k < kCand; k++) {
+      if (!ok[i][k] || bl >= cap[i]) continue;
+      uint32_t L;
+      if (cap[i] >= 8) {
+        const uint64_t x = v[i][k] ^ head[i];
+        L = x ? (uint32_t)__builtin_ctzll(x) >> 3 : match_rest(in, p[i], cs[i][k], cap[i]);
+      } else {
+        L = 0;
+        while (L < cap[i] && in[cs[i][k] + L] == in[p[i] + L]) L++;
+      }
+      if (L > bl) {
+        bl = L;
+        bd = p[i] - cs[i][k];
+      }
+    }
+    res[i] = bl >= 3 ? (bl | (bd << 9)) : 0u;
+  }
 }
-// best[p] for every position, kThreads positions at a time: the ring first
-// takes their candidates (every thread, after the previous positions' walks
-// are done), then each thread measures its position.
+// best[p] for every position, kStep positions at a time: the ring first takes
+// their candidates (every thread, after the previous positions' walks are
+// done), then each thread measures its kPer positions.
 __device__ void measure(const GMEM uint8_t* in, uint32_t n, uint32_t window, uint32_t max_match,
                         const GMEM uint32_t* cand, GMEM uint32_t* best) {
   const uint32_t t = threadIdx.x;
-  for (uint32_t P = 0; P < n; P += kThreads) {
-    const uint32_t p = P + t;
+  for (uint32_t P = 0; P < n; P += kStep) {
+    uint32_t p[kPer], res[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) p[i] = P + i * kThreads + t;
     __syncthreads();
-    if (p < n) s_lds[p % kRingC] = cand[p];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++)
+      if (p[i] < n) s_lds[p[i] % kRingC] = cand[p[i]];
     __syncthreads();
-    if (p < n) best[p] = best_match(in, n, window, max_match, p);
+    best_matches(in, n, window, max_match, p, res);
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++)
+      if (p[i] < n) best[p[i]] = res[i];
   }
 }
 
