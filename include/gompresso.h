@@ -162,8 +162,8 @@ typedef struct {
 #define GMP_STAT_SEG_REJECT 6   /* why segmented decoding was not accepted (then GMP_STAT_A2_PATH is 2), bits:
                                    1 index, 2 invalid code in a lane, 4 a lane's area overflowed, 8 lanes did
                                    not meet, 16 last lane's end, 32 open literal run, 64 per-sub-block counts,
-                                   128 repair failed; 0 when accepted or not attempted (after a second
-                                   attempt: the second attempt's reasons) */
+                                   128 repair failed; those of the last attempt that was not accepted (0
+                                   when the first attempt was accepted or none was made) */
 #define GMP_STAT_SEG_RETRY 7    /* further segmented attempts (0, 1 or 2) because lanes stayed out of step:
                                    a lane after a lane on the true symbol path restarts exactly at that
                                    lane's exit, the others warm up longer before their segment */

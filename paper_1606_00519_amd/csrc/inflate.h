@@ -51,7 +51,7 @@ __host__ __device__ inline uint64_t spill_bytes(uint32_t n_seq) { return 16 + 16
 //   [2] groups of 64 sequences, [3] groups resolved in window-sized pieces
 //   [4] groups of a DE block resolved by rounds because they break the DE rule
 //   [5] the wait that ran out first when the status is ESTALL (0: none)
-//   [6] why segmented decoding was not accepted (reason bits, 0: accepted)
+//   [6] why the last segmented attempt not accepted failed (reason bits; 0: none)
 //   [7] further segmented attempts (0-2)
 //   [8] back-references the first launch left to later launches (rounds per launch)
 //   [16 + r] back-reference bytes copied in round r + 1 (r < 64), all groups

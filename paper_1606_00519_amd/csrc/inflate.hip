@@ -272,7 +272,7 @@ __shared__ __attribute__((aligned(16))) uint32_t s_big[kRing / 4];     // lookup
 __shared__ __attribute__((aligned(16))) uint4 s_stage[kStageBytes / 16];  // bit rings, then staged tokens
 __shared__ Misc s_misc;
 __shared__ Seg s_seg;
-// exact restarts of the segmented decoder's second attempt (decode_segmented)
+// exact restarts of the segmented decoder's later attempts (decode_segmented)
 __shared__ uint32_t s_xstart[kMaxLanes];
 
 __device__ __forceinline__ uint8_t* ring_ptr() { return reinterpret_cast<uint8_t*>(s_big); }
@@ -1969,7 +1969,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
     g.p_end = t + 1 == kLanes ? 32 * pw : snap_boundary(128 * (uint32_t)((uint64_t)rows * (t + 1) / kLanes), n_sub);
     // the lane's bit ring starts at the row of the first bit it decodes
     g.overlap = overlap;
-    // a second attempt restarts a lane that fell out of step exactly where a
+    // a later attempt restarts a lane that fell out of step exactly where a
     // lane in step before it ended (its first symbol boundary at or after
     // this lane's segment start)
     g.xstart = second && s_xstart[t] < g.p_end ? s_xstart[t] : kDone;
@@ -2055,7 +2055,7 @@ __device__ bool decode_segmented(const DevJob& job, const GMEM uint8_t* idx, con
       // Which lanes are on the true symbol path from their entry on: lane 0,
       // lanes whose entry is a sub-block start, and lanes that met (or were
       // repaired from) the exit of a lane on it.  A lane that failed or did
-      // not meet its predecessor restarts, in a second attempt, exactly at
+      // not meet its predecessor restarts, in a later attempt, exactly at
       // that predecessor's exit when the predecessor is on the path.
       // A restart found once stays: the exit of a lane on the path is the
       // first true boundary at or after the next lane's segment start.
@@ -2361,9 +2361,10 @@ __device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t fla
   GMEM uint64_t* ws_seq = (GMEM uint64_t*)gmem(job.ws);
   GMEM uint8_t* ws_lit = gmem(job.ws) + 8ull * n_seq;
   // Lanes that stayed out of step past what their repair covers (codes that
-  // fall into step slowly) get a second attempt: a lane that follows a lane
-  // on the true path restarts exactly at that lane's exit, the others warm up
-  // far longer.  It costs less than decoding every sub-block in one lane.
+  // fall into step slowly) get up to two more attempts: a lane that follows a
+  // lane on the true path restarts exactly at that lane's exit (and keeps
+  // that start), the others warm up far longer.  It costs less than decoding
+  // every sub-block in one lane.
   bool segmented = false;
   for (uint32_t k = t; k < kMaxLanes; k += block_threads<kDec>()) s_xstart[k] = kDone;
 #pragma nounroll
@@ -2373,7 +2374,7 @@ __device__ __forceinline__ int prepare_bit_block(const DevJob& job, uint32_t fla
                                        attempt != 0);
     __syncthreads();  // the rejection reasons are in LDS for every thread
     // (an invalid code with lanes that did not meet is most often a lane out
-    // of step; a corrupt block fails the second attempt too)
+    // of step; a corrupt block fails the later attempts too)
     if (segmented || !(sh.seg_reject & (kRejMeet | kRejRepair)) || (sh.seg_reject & kRejIndex) || sh.abort ||
         (attempt > 0 && sh.seg_restarts == 0))
       break;
