@@ -15,8 +15,9 @@
 //   L  the workgroup takes 512 positions at a time; each thread walks its
 //      position's chain (up to kChain candidates within the window) in an
 //      LDS ring of the candidates' links, then loads the eight bytes at every
-//      candidate and at distances 1-4 at once and keeps the longest match
-//      (the first of equals);
+//      candidate and at distances 1-4 at once, extends the candidates that
+//      agree on all eight together, eight bytes a round, and keeps the
+//      longest match (the first of equals);
 //   P  each wavefront parses one eighth of the block greedily (a block
 //      under 64 KiB: wavefront 0 all of it): a literal run ends at the first
 //      position whose match (cut at the part's end, and under the DE rule) is
@@ -136,22 +137,14 @@ constexpr uint32_t kRingC = kWaves * kHashSize;
 constexpr uint32_t kReach = kRingC - kStep;
 constexpr uint32_t kCand = 4 + kChain;  // distances 1-4, then the chain
 
-// The rest of a match whose first eight bytes agree (p + cap <= n).
-__device__ __noinline__ uint32_t match_rest(const GMEM uint8_t* in, uint32_t p, uint32_t s, uint32_t cap) {
-  uint32_t L = 8;
-  for (; L + 8 <= cap; L += 8) {
-    const uint64_t x = *(const GMEM u64u*)(in + s + L) ^ *(const GMEM u64u*)(in + p + L);
-    if (x) return L + ((uint32_t)__builtin_ctzll(x) >> 3);
-  }
-  while (L < cap && in[s + L] == in[p + L]) L++;
-  return L;
-}
-
 // The best matches at kPer positions: length | distance << 9 (0 when none of
 // 3 bytes or more).  Distances 1-4 first (runs and short periods), then up to
 // kChain candidates of the hash chain; the longest wins, the first of
 // equals.  The chains are walked in LDS first; then the eight bytes at every
-// candidate of every position are loaded at once, so the loads overlap.
+// candidate of every position are loaded at once, so the loads overlap.  The
+// candidates whose eight bytes all agree are then extended together, eight
+// bytes a round with every such candidate's load in flight at once, so a
+// wavefront waits for one load per round, not one per candidate and round.
 __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n, uint32_t window,
                                              uint32_t max_match, const uint32_t (&p)[kPer],
                                              uint32_t (&res)[kPer]) {
@@ -191,19 +184,61 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
   }
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
-    uint32_t bl = 0, bd = 0;
-    for (uint32_t k = 0; k < kCand; k++) {
-      if (!ok[i][k] || bl >= cap[i]) continue;
-      uint32_t L;
-      if (cap[i] >= 8) {
+    uint32_t len[kCand];
+    if (cap[i] >= 8) {
+      uint32_t more = 0;  // bit k: candidate k agrees on every byte so far
+#pragma unroll
+      for (uint32_t k = 0; k < kCand; k++) {
         const uint64_t x = v[i][k] ^ head[i];
-        L = x ? (uint32_t)__builtin_ctzll(x) >> 3 : match_rest(in, p[i], cs[i][k], cap[i]);
-      } else {
-        L = 0;
-        while (L < cap[i] && in[cs[i][k] + L] == in[p[i] + L]) L++;
+        len[k] = !ok[i][k] ? 0u : x ? (uint32_t)__builtin_ctzll(x) >> 3 : 8u;
+        more |= (ok[i][k] && !x ? 1u : 0u) << k;
       }
-      if (L > bl) {
-        bl = L;
+      for (uint32_t off = 8; more && off < cap[i]; off += 8) {
+        if (p[i] + off + 8 <= n) {
+          // eight bytes at p + off and at every candidate still agreeing
+          // (candidates lie before p, so all of them are inside the block);
+          // the others load p + off again
+          const uint64_t h = *(const GMEM u64u*)(in + p[i] + off);
+          uint64_t w[kCand];
+#pragma unroll
+          for (uint32_t k = 0; k < kCand; k++)
+            w[k] = *(const GMEM u64u*)(in + ((more >> k) & 1u ? cs[i][k] : p[i]) + off);
+#pragma unroll
+          for (uint32_t k = 0; k < kCand; k++) {
+            const uint64_t y = w[k] ^ h;
+            if ((more >> k) & 1u) {
+              len[k] = y ? off + ((uint32_t)__builtin_ctzll(y) >> 3) : off + 8;
+              if (y) more &= ~(1u << k);
+            }
+          }
+        } else {
+          // the block's last bytes, one at a time
+#pragma unroll
+          for (uint32_t k = 0; k < kCand; k++) {
+            if (!((more >> k) & 1u)) continue;
+            uint32_t L = off;
+            while (L < cap[i] && in[cs[i][k] + L] == in[p[i] + L]) L++;
+            len[k] = L;
+          }
+          more = 0;
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kCand; k++) len[k] = min(len[k], cap[i]);
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < kCand; k++) {
+        uint32_t L = 0;
+        if (ok[i][k])
+          while (L < cap[i] && in[cs[i][k] + L] == in[p[i] + L]) L++;
+        len[k] = L;
+      }
+    }
+    uint32_t bl = 0, bd = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kCand; k++) {
+      if (ok[i][k] && len[k] > bl) {
+        bl = len[k];
         bd = p[i] - cs[i][k];
       }
     }
