@@ -7,22 +7,24 @@
 // back-reference (section "Dependency Elimination (DE)" and its compression
 // algorithm).  One workgroup compresses one block:
 //
-//   W  eight wavefronts each walk one eighth of the block, 64 positions at a
-//      time, through a hash table of 3-byte keys in LDS (preceded by the
-//      window before their eighth, so every position sees up to the window's
-//      history): every position gets the most recent earlier position with
-//      its key's hash, its candidate (the candidates form hash chains);
-//   L  the workgroup takes 512 positions at a time; each thread walks its
+//   W  the first eight of the workgroup's sixteen wavefronts each walk one
+//      eighth of the block, 64 positions at a time, through a hash table of
+//      3-byte keys in LDS (preceded by the window before their eighth, so
+//      every position sees up to the window's history): every position gets
+//      the most recent earlier position with its key's hash, its candidate
+//      (the candidates form hash chains);
+//   L  the workgroup takes 1024 positions at a time; each thread walks its
 //      position's chain (up to kChain candidates within the window) in an
 //      LDS ring of the candidates' links, then loads the eight bytes at every
 //      candidate and at distances 1-4 at once, extends the candidates that
 //      agree on all eight together, eight bytes a round, and keeps the
 //      longest match (the first of equals);
-//   P  each wavefront parses one eighth of the block greedily (a block
-//      under 64 KiB: wavefront 0 all of it): a literal run ends at the first
-//      position whose match (cut at the part's end, and under the DE rule) is
-//      at least 3 bytes long, found 64 positions at a time with a ballot; a
-//      run that reaches 255 bytes becomes a sequence of its own.  Under DE a
+//   P  each of the first eight wavefronts parses one eighth of the block
+//      greedily (a block under 64 KiB: wavefront 0 all of it): a literal run
+//      ends at the first position whose match (cut at the part's end, and
+//      under the DE rule) is at least 3 bytes long, found 64 positions at a
+//      time with a ballot; a run that reaches 255 bytes becomes a sequence of
+//      its own.  Under DE a
 //      part's records are padded with empty ones to a multiple of 64, so the
 //      next part starts a group.  The parts' records are then put in order;
 //   A  the whole workgroup writes the literal bytes after the records, from
@@ -39,7 +41,8 @@ namespace gmpc {
 
 #define GMEM __attribute__((address_space(1)))
 
-constexpr uint32_t kWaves = 8, kThreads = 64 * kWaves;
+constexpr uint32_t kWaves = 8;                                    // W's walkers and P's parts
+constexpr uint32_t kBlockWaves = 16, kThreads = 64 * kBlockWaves;  // the workgroup
 constexpr uint32_t kHashBits = 12, kHashSize = 1u << kHashBits;  // per walker
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kChain = 8;                  // candidates measured per position
@@ -50,7 +53,7 @@ constexpr int kOK = 0;
 __shared__ __attribute__((aligned(16))) uint32_t s_lds[kWaves * kHashSize];  // hash tables, then the match ring
 struct CMisc {
   uint32_t seg_seq[kWaves], seg_lit[kWaves];  // records and literal bytes of each part's parse
-  uint32_t wave_sum[2][kWaves];
+  uint32_t wave_sum[2][kBlockWaves];
 };
 __shared__ CMisc s_cm;
 
@@ -77,7 +80,7 @@ __device__ void block_excl_scan2(uint32_t& a, uint32_t& b, uint32_t& tot_a, uint
   }
   __syncthreads();
   uint32_t pa = 0, pb = 0, ta = 0, tb = 0;
-  for (uint32_t k = 0; k < kWaves; k++) {
+  for (uint32_t k = 0; k < kBlockWaves; k++) {
     const uint32_t x = s_cm.wave_sum[0][k], y = s_cm.wave_sum[1][k];
     if (k < w) {
       pa += x;
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   const uint32_t n = (uint32_t)job.in_len;
   __syncthreads();
   // W
-  walk(in, n, prm.window, cand, wave);
+  if (wave < kWaves) walk(in, n, prm.window, cand, wave);
   __threadfence();
   __syncthreads();
   // L
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   const uint32_t parts = n >= kSegMin ? kWaves : 1u;
   const uint32_t part = parts == 1 ? n : ((n + kWaves - 1) / kWaves + 63) & ~63u;
   const uint32_t lo = wave < parts ? min(n, wave * part) : n, hi = wave < parts ? min(n, lo + part) : n;
-  {
+  if (wave < kWaves) {
     uint32_t ns = 0, nl = 0;
     parse(best, lo, hi, prm.de, prm.de && wave + 1 < parts, cand + lo, ns, nl);
     if (lane == 0) {
