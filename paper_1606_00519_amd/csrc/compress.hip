@@ -24,9 +24,9 @@
 //      ends at the first position whose match (cut at the part's end, and
 //      under the DE rule) is at least 3 bytes long, found 64 positions at a
 //      time with a ballot; a run that reaches 255 bytes becomes a sequence of
-//      its own.  Under DE a
-//      part's records are padded with empty ones to a multiple of 64, so the
-//      next part starts a group.  The parts' records are then put in order;
+//      its own.  Under DE a part's records are padded with empty ones to a
+//      multiple of 64, so the next part starts a group.  The parts' records
+//      are then put in order;
 //   A  the whole workgroup writes the literal bytes after the records, from
 //      prefix sums over the records, then the header and zero padding.
 //
@@ -130,15 +130,20 @@ __device__ void walk(const GMEM uint8_t* in, uint32_t n, uint32_t window, GMEM u
 }
 
 // ---------------------------------------------------------------- L
-// Candidates' links, for the chain walks of L, live in an LDS ring of the
-// last kRingC positions (the hash tables' space): the workgroup measures
-// kStep positions at a time (kPer per thread), so a chain reaches
-// kRingC - kStep positions back at most.
+// Candidates' links, for the chain walks of L, live in an LDS ring (the hash
+// tables' space) of the last kRingC positions, as distances back (16 bits;
+// 0: none).  The workgroup measures kStep positions at a time (kPer per
+// thread).  A wavefront may store the next positions' links while another
+// still walks chains of the current ones, so a chain reaches back at most
+// kRingC - 2 kStep positions: the slots being overwritten are never read.
 constexpr uint32_t kPer = 1;
 constexpr uint32_t kStep = kPer * kThreads;
-constexpr uint32_t kRingC = kWaves * kHashSize;
-constexpr uint32_t kReach = kRingC - kStep;
+constexpr uint32_t kRingC = 2 * kWaves * kHashSize;
+constexpr uint32_t kReach = kRingC - 2 * kStep;
 constexpr uint32_t kCand = 4 + kChain;  // distances 1-4, then the chain
+static_assert(kRingC * sizeof(uint16_t) <= sizeof(s_lds), "the ring fits the hash tables' space");
+static_assert(kReach >= 32768, "a chain reaches a 32 KiB window");
+__device__ __forceinline__ uint16_t* link_ring() { return reinterpret_cast<uint16_t*>(s_lds); }
 
 // The best matches at kPer positions: length | distance << 9 (0 when none of
 // 3 bytes or more).  Distances 1-4 first (runs and short periods), then up to
@@ -164,7 +169,8 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
       ok[i][d - 1] = has && d <= p[i] && d <= window;
       cs[i][d - 1] = ok[i][d - 1] ? p[i] - d : p[i];
     }
-    c[i] = has ? s_lds[p[i] % kRingC] : kNone;
+    const uint32_t l = has ? link_ring()[p[i] % kRingC] : 0u;
+    c[i] = l ? p[i] - l : kNone;
     live[i] = has;
   }
 #pragma unroll
@@ -174,7 +180,8 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
       live[i] = live[i] && c[i] != kNone && c[i] < p[i] && p[i] - c[i] <= reach;
       ok[i][4 + k] = live[i] && p[i] - c[i] > 4;
       cs[i][4 + k] = ok[i][4 + k] ? c[i] : p[i];
-      c[i] = live[i] ? s_lds[c[i] % kRingC] : kNone;
+      const uint32_t l = live[i] ? link_ring()[c[i] % kRingC] : 0u;
+      c[i] = l ? c[i] - l : kNone;
     }
   }
   uint64_t head[kPer], v[kPer][kCand];
@@ -248,25 +255,22 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
     res[i] = bl >= 3 ? (bl | (bd << 9)) : 0u;
   }
 }
-// best[p] for every position, kStep positions at a time: the ring first takes
-// their candidates (every thread, after the previous positions' walks are
-// done), then each thread measures its kPer positions.
+// best[p] for every position, kStep positions at a time: each thread stores
+// its position's link (its candidate was loaded during the previous
+// positions' walks), then, after one barrier, measures it.
 __device__ void measure(const GMEM uint8_t* in, uint32_t n, uint32_t window, uint32_t max_match,
                         const GMEM uint32_t* cand, GMEM uint32_t* best) {
+  static_assert(kPer == 1, "one position per thread");
   const uint32_t t = threadIdx.x;
+  uint32_t next = t < n ? cand[t] : kNone;  // the candidate of the thread's next position (before it)
   for (uint32_t P = 0; P < n; P += kStep) {
-    uint32_t p[kPer], res[kPer];
-#pragma unroll
-    for (uint32_t i = 0; i < kPer; i++) p[i] = P + i * kThreads + t;
+    const uint32_t p = P + t;
+    if (p < n) link_ring()[p % kRingC] = (uint16_t)(next != kNone && p - next < 65536u ? p - next : 0u);
     __syncthreads();
-#pragma unroll
-    for (uint32_t i = 0; i < kPer; i++)
-      if (p[i] < n) s_lds[p[i] % kRingC] = cand[p[i]];
-    __syncthreads();
-    best_matches(in, n, window, max_match, p, res);
-#pragma unroll
-    for (uint32_t i = 0; i < kPer; i++)
-      if (p[i] < n) best[p[i]] = res[i];
+    next = p + kStep < n ? cand[p + kStep] : kNone;
+    uint32_t q[kPer] = {p}, res[kPer];
+    best_matches(in, n, window, max_match, q, res);
+    if (p < n) best[p] = res[0];
   }
 }
 
