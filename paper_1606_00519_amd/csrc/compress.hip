@@ -19,14 +19,13 @@
 //      candidate and at distances 1-4 at once, extends the candidates that
 //      agree on all eight together, eight bytes a round, and keeps the
 //      longest match (the first of equals);
-//   P  each of the first eight wavefronts parses one eighth of the block
-//      greedily (a block under 64 KiB: wavefront 0 all of it): a literal run
-//      ends at the first position whose match (cut at the part's end, and
-//      under the DE rule) is at least 3 bytes long, found 64 positions at a
-//      time with a ballot; a run that reaches 255 bytes becomes a sequence of
-//      its own.  Under DE a part's records are padded with empty ones to a
-//      multiple of 64, so the next part starts a group.  The parts' records
-//      are then put in order;
+//   P  each wavefront parses one sixteenth of the block greedily (a block
+//      under 64 KiB: wavefront 0 all of it): a literal run ends at the first
+//      position whose match (cut at the part's end, and under the DE rule) is
+//      at least 3 bytes long, found 64 positions at a time with a ballot; a
+//      run that reaches 255 bytes becomes a sequence of its own.  Under DE a
+//      part's records are padded with empty ones to a multiple of 64, so the
+//      next part starts a group.  The parts' records are then put in order;
 //   A  the whole workgroup writes the literal bytes after the records, from
 //      prefix sums over the records, then the header and zero padding.
 //
@@ -41,18 +40,19 @@ namespace gmpc {
 
 #define GMEM __attribute__((address_space(1)))
 
-constexpr uint32_t kWaves = 8;                                    // W's walkers and P's parts
+constexpr uint32_t kWaves = 8;                                    // W's walkers
 constexpr uint32_t kBlockWaves = 16, kThreads = 64 * kBlockWaves;  // the workgroup
+constexpr uint32_t kParts = kBlockWaves;                           // P's parts
 constexpr uint32_t kHashBits = 12, kHashSize = 1u << kHashBits;  // per walker
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kChain = 8;                  // candidates measured per position
-constexpr uint32_t kSegMin = 65536;             // blocks at least this long are parsed in kWaves parts
+constexpr uint32_t kSegMin = 65536;             // blocks at least this long are parsed in kParts parts
 constexpr uint32_t kMagicByte = 0x59504D47u;    // 'GMPY'
 constexpr int kOK = 0;
 
 __shared__ __attribute__((aligned(16))) uint32_t s_lds[kWaves * kHashSize];  // hash tables, then the match ring
 struct CMisc {
-  uint32_t seg_seq[kWaves], seg_lit[kWaves];  // records and literal bytes of each part's parse
+  uint32_t seg_seq[kParts], seg_lit[kParts];  // records and literal bytes of each part's parse
   uint32_t wave_sum[2][kBlockWaves];
 };
 __shared__ CMisc s_cm;
@@ -382,15 +382,15 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   for (uint32_t p = n + t; p < ((n + 255) & ~255u); p += kThreads) best[p] = 0;  // staging reads whole KiBs
   __threadfence();
   __syncthreads();
-  // P: a block of at least kSegMin bytes is parsed in kWaves parts at once
+  // P: a block of at least kSegMin bytes is parsed in kParts parts at once
   // (one per wavefront, into the candidate area, free after L; a match does
   // not cross a part's end), a shorter one by wavefront 0 alone; then the
   // parts' records go to the output, in order
   GMEM uint32_t* rec = (GMEM uint32_t*)(out + 32);
-  const uint32_t parts = n >= kSegMin ? kWaves : 1u;
-  const uint32_t part = parts == 1 ? n : ((n + kWaves - 1) / kWaves + 63) & ~63u;
+  const uint32_t parts = n >= kSegMin ? kParts : 1u;
+  const uint32_t part = parts == 1 ? n : ((n + kParts - 1) / kParts + 63) & ~63u;
   const uint32_t lo = wave < parts ? min(n, wave * part) : n, hi = wave < parts ? min(n, lo + part) : n;
-  if (wave < kWaves) {
+  if (wave < kParts) {
     uint32_t ns = 0, nl = 0;
     parse(best, lo, hi, prm.de, prm.de && wave + 1 < parts, cand + lo, ns, nl);
     if (lane == 0) {
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(const CompressJob* _
   __threadfence();
   __syncthreads();
   uint32_t n_seq = 0, n_lit = 0;
-  for (uint32_t w = 0; w < kWaves; w++) {
+  for (uint32_t w = 0; w < kParts; w++) {
     const uint32_t ns = s_cm.seg_seq[w];
     const GMEM uint32_t* src = cand + (w < parts ? min(n, w * part) : n);
     for (uint32_t i = t; i < ns; i += kThreads) rec[n_seq + i] = src[i];
