@@ -190,7 +190,7 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
     const bool wide = cap[i] >= 8;  // then every candidate's eight bytes lie inside the block
     head[i] = wide ? *(const GMEM u64u*)(in + p[i]) : 0ull;
 #pragma unroll
-    for (uint32_t k = 0; k < kCand; k++) v[i][k] = wide ? *(const GMEM u64u*)(in + cs[i][k]) : 0ull;
+    for (uint32_t k = 0; k < kCand; k++) v[i][k] = wide && ok[i][k] ? *(const GMEM u64u*)(in + cs[i][k]) : 0ull;
   }
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
@@ -206,13 +206,12 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
       for (uint32_t off = 8; more && off < cap[i]; off += 8) {
         if (p[i] + off + 8 <= n) {
           // eight bytes at p + off and at every candidate still agreeing
-          // (candidates lie before p, so all of them are inside the block);
-          // the others load p + off again
+          // (candidates lie before p, so all of them are inside the block)
           const uint64_t h = *(const GMEM u64u*)(in + p[i] + off);
           uint64_t w[kCand];
 #pragma unroll
           for (uint32_t k = 0; k < kCand; k++)
-            w[k] = *(const GMEM u64u*)(in + ((more >> k) & 1u ? cs[i][k] : p[i]) + off);
+            w[k] = (more >> k) & 1u ? *(const GMEM u64u*)(in + cs[i][k] + off) : 0ull;
 #pragma unroll
           for (uint32_t k = 0; k < kCand; k++) {
             const uint64_t y = w[k] ^ h;
