@@ -189,8 +189,16 @@ __device__ __forceinline__ void best_matches(const GMEM uint8_t* in, uint32_t n,
   for (uint32_t i = 0; i < kPer; i++) {
     const bool wide = cap[i] >= 8;  // then every candidate's eight bytes lie inside the block
     head[i] = wide ? *(const GMEM u64u*)(in + p[i]) : 0ull;
+    // distances 1-4 from the eight bytes before p and the eight at p
+    const bool near = wide && p[i] >= 8;
+    const uint64_t before = near ? *(const GMEM u64u*)(in + p[i] - 8) : 0ull;
 #pragma unroll
-    for (uint32_t k = 0; k < kCand; k++) v[i][k] = wide && ok[i][k] ? *(const GMEM u64u*)(in + cs[i][k]) : 0ull;
+    for (uint32_t k = 0; k < kCand; k++) {
+      const bool from_regs = k < 4 && near;  // distance k + 1
+      v[i][k] = !(wide && ok[i][k]) ? 0ull
+                : from_regs        ? (before >> (8 * (7 - k))) | (head[i] << (8 * (k + 1)))
+                                   : *(const GMEM u64u*)(in + cs[i][k]);
+    }
   }
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
