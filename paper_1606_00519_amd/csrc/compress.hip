@@ -11,8 +11,8 @@
 //      eighth of the block, 64 positions at a time, through a hash table of
 //      3-byte keys in LDS (preceded by the window before their eighth, so
 //      every position sees up to the window's history): every position gets
-//      the most recent earlier position with its key's hash, its candidate
-//      (the candidates form hash chains);
+//      the most recent position with its key's hash in an earlier group of
+//      64, its candidate (the candidates form hash chains);
 //   L  the workgroup takes 1024 positions at a time; each thread walks its
 //      position's chain (up to kChain candidates within the window) in an
 //      LDS ring of the candidates' links, then loads the eight bytes at every

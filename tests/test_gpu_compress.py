@@ -107,6 +107,28 @@ def test_ratio_against_cpu_compressor(ctx, kind, de):
     assert gpu <= 1.25 * cpu
 
 
+@pytest.mark.parametrize("name,period,max_lits", [("zeros", 1, 1), ("period17", 17, 64)])
+def test_matches_reach_max_match(ctx, name, period, max_lits):
+    # A run of one byte and a period of 17.  The greedy parse takes literals
+    # until the first match (a run: from position 1, at distance 1, from the
+    # bytes beside p; the period: once the hash walk, which links a position
+    # only to positions of earlier groups of 64, offers one, so within the
+    # first 64), then matches of max_match bytes at a multiple of the period
+    # until the last, which the block's end cuts: every candidate is extended
+    # to the cap.  The block stays under 64 KiB, which the GPU parses in one
+    # part (larger blocks are parsed in parts that no match crosses).
+    data = INPUTS[name][:60000]
+    (blk,) = gpu_compress(ctx, data, 1 << 20, 0)
+    rc, seqs, _ = oracle.block_tokens(blk)
+    assert rc == 0
+    lits = int(seqs[0, 0])
+    assert period <= lits <= max_lits and np.all(seqs[1:, 0] == 0)
+    m = seqs[:, 1] > 0
+    assert np.all(seqs[m, 2] % period == 0)
+    assert np.all(seqs[m, 1][:-1] == 258) and 3 <= seqs[m, 1][-1] <= 258
+    assert lits + int(seqs[m, 1].sum()) == len(data)
+
+
 def test_window_and_match_limits(ctx):
     data = INPUTS["text"][:1 << 20]
     for window, max_match in ((8192, 64), (1024, 16), (32768, 3)):
